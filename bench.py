@@ -1,0 +1,186 @@
+"""Benchmark: -2 ln L + gradient evaluations per second on one MI355X.
+
+Workload (default): D+ -> pi- pi+ pi+, 10M toy events generated on the device by accept-reject at
+the truth parameters, 10M uniform phase-space normalisation points, 50 S-wave knots, rho(770) and
+f2(1270), efficiency from a 200x200 FP32 table; mixed precision (FP32 streams and amplitudes, FP64
+accumulation and finish).  One step = one full evaluation (parameter upload, spline setup, the
+streaming forward+adjoint kernel over both point sets, reduction, FP64 finish, result readback).
+The plain FP64 GPU path is timed on the same workload and reported beside it, and the FP64 oracle is
+timed on a bounded sample on the host (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cpu] [--no-fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stream_bytes_per_point(precision_bytes: int, n_res: int, kind: str) -> int:
+    """Bytes the streaming kernel must read per point: (t12, t13) + one complex amplitude per resonance
+    (+ the weight for normalisation points)."""
+    b = 2 * precision_bytes + 2 * n_res * precision_bytes
+    return b + (precision_bytes if kind == "norm" else 0)
+
+
+def build_inputs(wl, n_events, n_norm):
+    import synth
+    from paper_1703_03284_amd import FP64, context_for
+    d = wl.decay
+    table = synth.efficiency_histogram(synth.PolyEfficiency.seeded(d, wl.seed("eff")))
+    truth = wl.truth()
+    t0 = time.time()
+    gen = context_for(d, wl.knots(), wl.resonances, FP64)
+    gen.set_eff_table(table, d.smin, d.smax)
+    ev12, ev13, fmax = gen.toy(truth, n_events, wl.seed("events"))
+    gen.close()
+    log(f"[bench] generated {n_events} toy events on the device in {time.time() - t0:.1f}s (fmax={fmax:.4g})")
+    t0 = time.time()
+    n12, n13 = synth.uniform_phase_space(d, n_norm, wl.seed("norm"))
+    area = synth.region_area_mc(d, 1 << 22, 5)  # only used as a constant weight scale
+    w = np.full(n_norm, area / n_norm)
+    log(f"[bench] normalisation points in {time.time() - t0:.1f}s")
+    return table, (ev12, ev13), (n12, n13, w)
+
+
+def time_gpu(wl, precision, table, events, norm, steps, warmup, blocks=0, waves=0):
+    from paper_1703_03284_amd import context_for
+    d = wl.decay
+    ctx = context_for(d, wl.knots(), wl.resonances, precision)
+    if blocks or waves:
+        ctx.set_launch(blocks, waves)
+    ctx.set_eff_table(table, d.smin, d.smax)
+    t0 = time.time()
+    ctx.load_events(*events)
+    ctx.load_norm(*norm)
+    log(f"[bench] loaded {len(events[0])} + {len(norm[0])} points in {time.time() - t0:.1f}s")
+    th0 = wl.start()
+    rng = np.random.Generator(np.random.PCG64(12345))
+    n_shape = 4 * wl.n_res
+    for _ in range(warmup):
+        ctx.eval(th0)
+    thetas = []
+    for _ in range(steps):
+        th = th0.copy()
+        th[:-n_shape] += 1e-9 * rng.standard_normal(len(th) - n_shape)  # no result can be reused
+        thetas.append(th)
+    dev_total, dev_stream = [], []
+    t0 = time.perf_counter()
+    for th in thetas:
+        ctx.eval(th)
+        a, b = ctx.timing()
+        dev_total.append(a)
+        dev_stream.append(b)
+    wall = time.perf_counter() - t0
+    nll, _ = ctx.eval(th0)
+    ctx.close()
+    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "value": steps / wall,
+            "dev_ms": float(np.mean(dev_total)), "stream_kernel_ms": float(np.mean(dev_stream)),
+            "stream_kernel_ms_median": float(np.median(dev_stream)), "nll": nll}
+
+
+def cpu_baseline(wl, n_events, n_norm, sample=2_000_000, reps=3):
+    """The oracle, as it is, on a bounded sample on one host core; scaled to the full workload."""
+    import synth
+    from threadpoolctl import threadpool_limits
+    from oracle import Model, Res
+    from oracle import kinematics as K
+    from oracle import likelihood as L
+    d = wl.decay
+    m = Model(d.M, d.m1, d.m2, d.m3, d.rD, tuple(wl.knots()),
+              tuple(Res(r.spin, r.mass, r.width, r.radius) for r in wl.resonances))
+    ev = synth.uniform_phase_space(d, sample, 1)
+    s12, s13 = synth.uniform_phase_space(d, sample, 2)
+    nm = (s12, s13, np.full(sample, K.area(m) / sample))
+    ts = []
+    with threadpool_limits(limits=1):
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            L.nll_and_grad(m, wl.start(), ev, nm, shapes=False)
+            ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    scale = (n_events + n_norm) / (2 * sample)
+    return {"value": 1.0 / (t * scale), "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample} events + {sample} normalisation points, median of {reps}, "
+                      f"scaled x{scale:.0f} to the full workload; {t:.2f} s per sample evaluation"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--events", type=int, default=None)
+    ap.add_argument("--norm", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the likelihood would shard "
+              "by points with one small all-reduce per evaluation; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import synth
+    from paper_1703_03284_amd import FP64, MIXED
+    wl = synth.C3
+    n_ev = args.events or wl.n_events
+    n_nm = args.norm or wl.n_norm
+    table, events, norm = build_inputs(wl, n_ev, n_nm)
+    mixed = time_gpu(wl, MIXED, table, events, norm, args.steps, args.warmup, args.blocks, args.waves)
+    log(f"[bench] mixed: {mixed}")
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = time_gpu(wl, FP64, table, events, norm, args.steps, args.warmup, args.blocks, args.waves)
+        log(f"[bench] fp64: {fp64}")
+    bytes_launch = n_ev * stream_bytes_per_point(4, wl.n_res, "data") + \
+        n_nm * stream_bytes_per_point(4, wl.n_res, "norm")
+    achieved = bytes_launch / (mixed["stream_kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "NLL+grad evals/sec @10M events (mixed vs FP64 GPU)",
+        "value": mixed["value"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D+->pi-pi+pi+ {n_ev} toy events + {n_nm} uniform normalisation points, "
+                               f"{wl.n_knots} knots, rho(770)+f2(1270), 200x200 efficiency table, mixed precision",
+                   "events": n_ev, "norm_points": n_nm, "knots": wl.n_knots, "resonances": wl.n_res,
+                   "accumulate": "f64"},
+        "device_ms_per_step": mixed["dev_ms"],
+        "fp64": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+                                           "device_ms_per_step": fp64["dev_ms"],
+                                           "stream_kernel_ms": fp64["stream_kernel_ms"],
+                                           "mixed_speedup": mixed["value"] / fp64["value"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_eval<float,2,false>", "bytes_per_launch": bytes_launch,
+                     "kernel_ms": mixed["stream_kernel_ms"]},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, n_ev, n_nm)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

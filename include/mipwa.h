@@ -1,0 +1,190 @@
+/*
+ * mipwa.h -- C ABI of libmipwa, an MI355X (gfx950) engine for the unbinned likelihood of a
+ * model-independent partial-wave analysis (MIPWA) of D+ -> h- h+ h+.
+ *
+ * The method is that of "Model-independent partial wave analysis using a massively-parallel
+ * fitting framework" (Sun, Aoude, dos Reis, Sokoloff):
+ *   Sec. 2, Eq. 1  A(s12, s13) = sum_L sum_k c_k^L A_k^L(s12, s13), truncated at L = 2;
+ *   Sec. 2         P/D waves: relativistic Breit-Wigner times a real spin-dependent angular factor;
+ *   Sec. 2         S-wave: N boundary points s_k spanning the m^2(h+h-) spectrum, A_0(s_k) =
+ *                  a_k exp(i phi_k) with a_k, phi_k free, and a cubic spline in the complex plane in
+ *                  between (read as: natural spline of Re and Im through z_k = a_k exp(i phi_k));
+ *   Sec. 4         Bose symmetrisation over the two h+h- axes: every amplitude is f(s12,s13)+f(s13,s12);
+ *   Sec. 2, Sec. 4 unbinned maximum likelihood, with the normalisation integral recomputed from points
+ *                  spread over the Dalitz plane in every iteration.
+ * The quantity evaluated is
+ *   -2 ln L = -2 sum_i ln|A(x_i)|^2 - 2 sum_i ln eps(x_i) + 2 n ln I,   I = sum_j w_j eps_j |A(x_j)|^2.
+ *
+ * Conventions
+ *   Units: GeV, GeV^2, GeV^-1.  Particle 1 is the h-, particles 2 and 3 the identical h+ (m2 == m3).
+ *   Parameter vector theta (P = 2N + 4R doubles):
+ *     [a_0, phi_0, ..., a_{N-1}, phi_{N-1},  |c_1|, arg c_1, ..., |c_R|, arg c_R,  m_1, G_1, ..., m_R, G_R]
+ *   The S-wave is component 0 of Eq. 1 with coefficient 1.
+ *   Every function returns an int status: MIPWA_OK (0) or a negative MIPWA_E_* code; no C++ exception
+ *   crosses the ABI.  On error, mipwa_last_error(ctx) holds a message.
+ *   A context is used by one thread at a time; separate contexts may be used from separate threads.
+ *   Host input arrays are copied before a call returns; output arrays are allocated by the caller.
+ */
+#ifndef MIPWA_H
+#define MIPWA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { MIPWA_FP64 = 0, MIPWA_MIXED = 1 };
+
+enum {
+  MIPWA_OK = 0,
+  MIPWA_E_INVAL = -1,      /* bad argument: sizes, masses, knots, points outside the Dalitz region */
+  MIPWA_E_NOMEM = -2,      /* device or pinned host allocation failed, or a budget was exceeded */
+  MIPWA_E_HIP = -3,        /* a HIP runtime call failed */
+  MIPWA_E_STATE = -4,      /* call out of order (e.g. eval before events, params or norm points) */
+  MIPWA_E_DOMAIN = -5,     /* non-finite -2 ln L (|A|^2 = 0 at an event); the value is +inf */
+  MIPWA_E_NOCONV = -6,     /* the minimiser stopped without reaching the requested EDM */
+  MIPWA_E_CANCELLED = -7,  /* a serving job was cancelled */
+  MIPWA_E_BUSY = -8        /* a serving job has no result yet */
+};
+
+enum { MIPWA_MAX_KNOTS = 128, MIPWA_MAX_RES = 4 };
+
+/* One P- or D-wave resonance (Sec. 2: spin-dependent relativistic Breit-Wigner).
+ * spin in {0,1,2}; mass and width > 0; radius >= 0 is the Blatt-Weisskopf radius of the resonance.
+ * The running width is Gamma(x) = width (q/q_r)^(2L+1) (mass/sqrt(x)) B_L(q,q_r)^2; barrier factors
+ * B_L(q,q_r; radius) B_L(p,p_r; rD) with p the bachelor momentum in the resonance frame; Zemach
+ * angular factors T_1, T_2. */
+typedef struct {
+  int spin;
+  double mass;
+  double width;
+  double radius;
+} mipwa_res;
+
+/* Decay kinematics, D barrier radius rD >= 0, the N strictly increasing knot positions in m^2(h+h-)
+ * (Sec. 2 boundary points; 3 <= N <= MIPWA_MAX_KNOTS) and R <= MIPWA_MAX_RES resonances. */
+typedef struct {
+  double M, m1, m2, m3, rD;
+  int n_knots;
+  const double* knots;
+  int n_res;
+  const mipwa_res* res;
+} mipwa_model;
+
+typedef struct mipwa_ctx mipwa_ctx;
+
+/* Create a context on HIP device `device` computing in `precision` (MIPWA_FP64: all device arithmetic
+ * in FP64; MIPWA_MIXED: FP32 point streams, amplitudes and spline, FP64 accumulation and host finish).
+ * Errors: E_INVAL for an invalid model (m2 != m3, knots not increasing or out of range, spin outside
+ * 0..2, width <= 0, radius < 0, a mass below its two-body threshold or above M - m3); E_HIP. */
+int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx** out);
+void mipwa_destroy(mipwa_ctx* ctx);
+/* Message for the last failed call on ctx (never NULL; empty if none).  Valid until the next call. */
+const char* mipwa_last_error(const mipwa_ctx* ctx);
+const char* mipwa_strerror(int status);
+int mipwa_n_params(const mipwa_ctx* ctx);
+
+/* Data events (the sample whose likelihood is maximised, Sec. 2).  s12[i], s13[i] are host arrays of n
+ * doubles, each event inside the Dalitz region to within 1e-9 (M - m3)^2.  eff (nullable) gives the
+ * efficiency at each event; it enters only the constant -2 sum ln eff.  If eff is NULL and an efficiency
+ * table was set with mipwa_set_eff_table, the table is used; otherwise eff = 1.  Events are reordered
+ * internally (the two h+h- coordinates of an event may be swapped: |A|^2 is symmetric, Sec. 4).
+ * Replaces previously loaded events.  Errors: E_INVAL (n < 1, non-finite or outside values, eff <= 0). */
+int mipwa_load_events(mipwa_ctx* ctx, const double* s12, const double* s13, const double* eff, int64_t n);
+
+/* Normalisation points (Sec. 4: points over the Dalitz plane used to normalise the PDF each
+ * iteration).  w[j] > 0 is the weight of point j (|D|/n for uniform phase-space points, the cell area for
+ * a grid); eff as for mipwa_load_events.  I = sum_j w_j eff_j |A_j|^2.  Errors as mipwa_load_events. */
+int mipwa_load_norm(mipwa_ctx* ctx, const double* s12, const double* s13, const double* w,
+                    const double* eff, int64_t n);
+
+/* Efficiency table: nx x ny float32 values at the bin centres of [lo, hi]^2 (row-major, index
+ * [i12 * ny + i13]), read by bilinear interpolation between centres, constant beyond the outermost
+ * centres.  Applied at the next mipwa_load_events / mipwa_load_norm whose eff argument is NULL.
+ * Errors: E_INVAL (nx, ny < 2, hi <= lo, a value <= 0). */
+int mipwa_set_eff_table(mipwa_ctx* ctx, const float* table, int nx, int ny, double lo, double hi);
+
+/* Parameters held fixed (fixed[p] != 0) in mipwa_fit.  The same mask selects whether mass and width
+ * partials are evaluated: when every mass and width is fixed (the default) the resonance amplitudes are
+ * cached on the device and rebuilt only when a mass or width changes, and the mass/width entries of the
+ * gradient are returned as 0; when any is floated the amplitudes and their mass/width derivatives are
+ * computed on the fly in every evaluation.  Errors: E_INVAL (n != P). */
+int mipwa_set_fixed(mipwa_ctx* ctx, const unsigned char* fixed, int n);
+
+/* Set theta (P doubles, layout above).  Errors: E_INVAL (n != P, non-finite values, a width <= 0 or a
+ * mass outside its kinematic range). */
+int mipwa_set_params(mipwa_ctx* ctx, const double* theta, int n);
+
+/* -2 ln L and its gradient at the current theta.  grad (nullable) receives P doubles.  Synchronous.
+ * Errors: E_STATE (no events, norm points or params), E_DOMAIN (non-finite value: *nll = +inf), E_HIP. */
+int mipwa_eval(mipwa_ctx* ctx, double* nll, double* grad);
+
+/* As mipwa_eval, asynchronously on `hip_stream` (a hipStream_t owned by the caller; NULL = the null
+ * stream): d_out is a device pointer to 1 + P doubles that receives [-2 ln L, grad...] when the stream
+ * reaches it.  The caller owns d_out and the stream.  No host synchronisation on the result; a
+ * non-finite value is not reported as E_DOMAIN (inspect d_out). */
+int mipwa_eval_async(mipwa_ctx* ctx, void* hip_stream, double* d_out);
+
+/* Component integrals over the normalisation points (Sec. 2, Eq. 1 components; component 0 = S-wave,
+ * r = 1..R the resonances at the current theta): I_jk = sum_p w_p [eff_p] A_j A_k^*, K = R + 1.
+ * with_eff = 0 omits the efficiency (for fit fractions).  Ijk receives 2 K K doubles (re, im), row-major. */
+int mipwa_integrals(mipwa_ctx* ctx, int with_eff, double* Ijk);
+
+/* Fit fractions FF_jk = Re(c_j c_k^* I_jk) / sum_jk c_j c_k^* I_jk at the current theta, with I
+ * computed without efficiency; ff receives K K doubles.  */
+int mipwa_fit_fractions(mipwa_ctx* ctx, double* ff);
+
+/* Maximum-likelihood fit (Sec. 2: {a_k, phi_k} and the c's determined by an unbinned ML fit; Sec. 4:
+ * normalisation recomputed every iteration).  Quasi-Newton BFGS with a strong-Wolfe line search over the
+ * parameters not marked fixed (mipwa_set_fixed), from theta_inout; stops when the estimated distance to
+ * the minimum EDM = g^T B g / 2 (B the inverse-Hessian estimate) falls below tol_edm.  Then H is taken by
+ * central differences of the analytic gradient, cov = 2 H^-1 over the floated parameters (zero rows for
+ * fixed ones), and each (magnitude, phase) pair is folded to magnitude >= 0, phase in (-pi, pi].
+ * cov_out (nullable) receives P*P doubles.  Errors: E_NOCONV (max_iter reached; results still
+ * written), E_STATE, E_DOMAIN (start point non-finite). */
+typedef struct {
+  double tol_edm;   /* default 1e-6 if <= 0 */
+  int max_iter;     /* default 1000 if <= 0 */
+  int hessian;      /* 1: finite-difference Hessian and covariance at the end; 0: skip (cov from B) */
+} mipwa_fit_opts;
+typedef struct {
+  double nll, edm;
+  int n_iter, n_eval, status;
+} mipwa_fit_info;
+int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* theta_inout, double* cov_out,
+              mipwa_fit_info* info);
+
+/* Toy Monte Carlo (Sec. 4: samples generated from the Dalitz-plot PDF) by accept-reject on
+ * f = |A|^2 eff at theta, on the device.  Candidate i uses Philox4x32-10 (Salmon et al., SC'11) with
+ * counter (i mod 2^32, i div 2^32, stream, 0) and key (seed mod 2^32, seed div 2^32): stream 0 gives
+ * (u12, u13), stream 1 gives v, each double from two words as ((a>>5) 2^26 + (b>>6)) 2^-53; the
+ * candidate is s = smin + (smax - smin) u, kept if inside the Dalitz region and f > v fmax.  The first n
+ * accepted candidates in candidate order are written to the host arrays s12_out, s13_out.  The
+ * efficiency is the table of mipwa_set_eff_table if set, else 1.  *exceeded (nullable) is set to 1 if
+ * any examined candidate had f > fmax (the sample is then not exact: raise fmax and repeat);
+ * *n_candidates (nullable) receives the number of candidates examined.  Does not change the context's
+ * loaded points.  Errors: E_INVAL (n < 1, fmax <= 0, wrong theta length). */
+int mipwa_generate(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t seed, double fmax,
+                   int64_t n, double* s12_out, double* s13_out, int* exceeded, int64_t* n_candidates);
+
+/* Largest f = |A|^2 eff over the first n_probe candidates inside the Dalitz region of key `seed`
+ * (same candidate stream as mipwa_generate). */
+int mipwa_density_max(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t seed, int64_t n_probe,
+                      double* fmax_out);
+
+/* Device time of the most recent evaluation's kernels in milliseconds (HIP events around the resonance
+ * cache build, the streaming likelihood kernel and the reduction); *stream_ms is the streaming kernel
+ * alone.  Nullable outputs. */
+int mipwa_last_timing(const mipwa_ctx* ctx, double* total_ms, double* stream_ms);
+
+/* Launch shape of the streaming kernel: blocks (0 = default) and waves per block (0 = default, 1..16).
+ * Takes effect at the next load.  Errors: E_INVAL. */
+int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves_per_block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIPWA_H */

@@ -1,0 +1,57 @@
+// The opaque context behind mipwa_ctx*.  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "host.h"
+
+struct mipwa_ctx {
+  int device = 0;
+  bool fp64 = true;
+  mipwa::ModelHost mh;
+  hipStream_t stream = nullptr;
+  mipwa::PointSet ev, nm;
+  mipwa::EffTable eff;
+
+  std::vector<double> theta;
+  bool have_theta = false;
+  std::vector<unsigned char> fixed;
+  bool otf = false;
+
+  std::vector<double> cache_shape;
+  bool cache_valid = false;
+
+  // [Real evaluation table | pad to 256 B | FP64: theta, K^T, h]
+  mipwa::DevBuf d_blob;
+  mipwa::HostBuf h_blob;
+  size_t tab64_off = 0, upload_bytes = 0;
+
+  mipwa::DevBuf d_segs, d_block_seg, d_records, d_fin, d_counter, d_out, d_job;
+  mipwa::HostBuf h_out;
+  mipwa::Segment h_segs[2];
+  int blocks_cfg = 1024, waves_cfg = 4;
+  int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0;
+  bool launch_dirty = true;
+
+  hipEvent_t ev_upload = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;
+  bool timing_pending = false;
+
+  std::string err;
+
+  ~mipwa_ctx() {
+    for (hipEvent_t e : {ev_upload, ev_t0, ev_t1, ev_t2, ev_t3})
+      if (e) (void)hipEventDestroy(e);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+
+  int fail(int code, const std::string& msg);
+  int rebuild_launch();
+  int stage_params();
+  bool shapes_changed() const;
+  int ensure_cache(hipStream_t st);
+  int enqueue_eval(hipStream_t st);
+};

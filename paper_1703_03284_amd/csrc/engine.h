@@ -1,0 +1,113 @@
+// Internal interface between the host library (mipwa.cpp) and the gfx950 kernels (kernels.hip).
+// Not installed; the public boundary is include/mipwa.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mipwa {
+
+// Points per tile.  A tile holds points of a single spline cell (j12, j13), so inside a tile both
+// interval indices are wave-uniform.
+constexpr int kTile = 256;
+constexpr int kMaxWaves = 16;
+constexpr int kMaxRes = 4;
+constexpr int kMaxKnots = 128;
+// Words per resonance in the evaluation table:
+// m^2, kappa, delta, rho^2, L, m, dln(kappa)/dm, d(delta)/dm, d(delta)/dGamma, unused.
+constexpr int kResWords = 10;
+
+struct Tile {
+  int j12, j13, start, count;
+};
+
+// Decay kinematics, precomputed on the host in FP64 and passed by value in working precision.
+template <typename Real>
+struct Kin {
+  Real sum;             // M^2 + m1^2 + m2^2 + m3^2 (so s23 = sum - s12 - s13)
+  Real thr_hi, thr_lo;  // (m1+m2)^2, (m1-m2)^2:  q^2 = (x - thr_hi)(x - thr_lo) / (4x)
+  Real pb_hi, pb_lo;    // (M+m3)^2, (M-m3)^2:    p^2 = (x - pb_hi)(x - pb_lo) / (4x)
+  Real t1corr;          // (M^2 - m3^2)(m1^2 - m2^2)
+  Real t2a, t2b;        // 2M^2 + 2m3^2, (M^2 - m3^2)^2
+  Real t2c, t2d;        // 2m1^2 + 2m2^2, (m1^2 - m2^2)^2
+  Real rD2;             // D barrier radius squared
+};
+
+// One stream of points (data events or normalisation points of one job) and where its per-block
+// partial records go.  Lives in device memory; read with uniform (scalar) loads.
+struct Segment {
+  const void* tt;     // Real2[n]: (t12, t13), local spline coordinates of the two h+h- invariants
+  const void* ss;     // Real2[n]: (s12, s13), canonical order s12 <= s13
+  const void* w;      // Real[n]: weight x efficiency (normalisation points), nullptr for data
+  const void* cache;  // Real2[R][n]: symmetrised resonance amplitudes R_r at each point
+  const Tile* tiles;
+  const void* table;  // evaluation table in working precision (spline polynomials, c, resonances)
+  double* records;    // n_blocks x rs
+  long long n;        // number of points
+  int n_tiles;
+  int kind;           // 0 = data, 1 = normalisation
+  int nint;           // N - 1 spline intervals
+  int rs;             // record size in doubles
+  int block0, n_blocks;
+  int pad0, pad1;
+};
+
+// One likelihood evaluation to finish: its two segments' records and the FP64 host table.
+struct Job {
+  const double* rec_d;  // data segment records
+  const double* rec_n;  // normalisation segment records
+  double* fin;          // 2 * rs scratch: reduced data record, reduced normalisation record
+  const double* tab64;  // theta[P], K^T[N*N], h[N-1]
+  double* out;          // 1 + P: -2 ln L, gradient
+  unsigned int* counter;
+  double n_ev;
+  double c_eps;         // -2 sum ln eff over the events
+  int nb_d, nb_n;
+  int N, R, rs, otf;
+  int n_chunks;
+  int pad;
+};
+
+// Record layout (doubles): [8 * nint spline-polynomial partials (interval j, power m, re/im)]
+// [sum] [2R: sum g conj(R_r)] [OTF: 2R sum g conj(dR_r/dm), 2R sum g conj(dR_r/dGamma)].
+inline int record_size(int nint, int R, bool otf) { return 8 * nint + 1 + 2 * R + (otf ? 4 * R : 0); }
+inline int table_words(int nint, int R) { return 8 * nint + 2 * R + kResWords * R; }
+
+// ---- launchers (kernels.hip); all asynchronous on `stream` ----
+hipError_t launch_cache(bool fp64, int R, const Segment* h_seg, const void* table, const void* kin,
+                        hipStream_t stream);
+hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* d_segs, const int* d_block_seg,
+                       int n_blocks, int waves, int max_nint, const void* kin, hipStream_t stream);
+hipError_t launch_finish(const Job* d_jobs, int n_jobs, int max_chunks, int max_N, hipStream_t stream);
+hipError_t launch_integrals(bool fp64, int R, const Segment* h_seg, const void* w_override,
+                            double* d_records, int n_blocks, double* d_out, hipStream_t stream);
+hipError_t launch_eff_lookup(const double* d_s12, const double* d_s13, long long n, const float* d_table,
+                             int nx, int ny, double lo, double hi, double* d_eps, hipStream_t stream);
+
+// Toy generation: candidate evaluation + order-preserving compaction (FP64).
+struct GenArgs {
+  const double* poly;   // 8 * (N - 1) spline polynomial coefficients
+  const double* knots;  // N
+  const double* c;      // 2R
+  const double* res;    // kResWords * R
+  const float* eff;     // nx * ny or nullptr
+  int N, R, nx, ny;
+  double eff_lo, eff_hi;
+  double M, m1, m2, m3; // kinematics for the region test
+  double smin, span;    // candidate box
+  unsigned long long seed;
+  double fmax;
+  int mode;             // 0: keep inside && f > v fmax; 1: keep inside (for the density maximum)
+  int pad;
+};
+hipError_t launch_generate_chunk(const GenArgs& g, const void* kin, long long first, int count,
+                                 double* d_s12, double* d_s13, double* d_f, unsigned char* d_flag,
+                                 int* d_block_counts, int* d_exceeded, hipStream_t stream);
+hipError_t launch_compact(const unsigned char* d_flag, int count, const int* d_block_counts,
+                          int* d_block_offsets, int* d_total, const double* a, const double* b,
+                          const double* c, double* out_a, double* out_b, double* out_c,
+                          hipStream_t stream);
+constexpr int kGenBlock = 1024;
+
+}  // namespace mipwa

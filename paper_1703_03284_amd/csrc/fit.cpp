@@ -1,0 +1,345 @@
+// Maximum-likelihood fit on top of mipwa_eval (Sec. 2: the knot parameters and the resonance
+// coefficients are determined by an unbinned ML fit; interpolation correlates them, so a robust
+// quasi-Newton minimiser is used; Sec. 4: the normalisation is recomputed in every iteration).
+//
+// BFGS on the floated parameters: inverse-Hessian estimate B (scaled identity after the first step),
+// search direction -B g, line search satisfying the strong Wolfe conditions (bracketing, then zoom
+// with safeguarded cubic interpolation; Nocedal & Wright, Numerical Optimization, ch. 3), update
+// B <- (I - rho s y^T) B (I - rho y s^T) + rho s s^T when s^T y > 0.  Convergence when
+// EDM = g^T B g / 2 < tol.  Then H by central differences of the analytic gradient, cov = 2 H^-1
+// (the objective is -2 ln L).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+#include "mipwa.h"
+
+namespace {
+
+struct Objective {
+  mipwa_ctx* ctx;
+  std::vector<int> free;
+  std::vector<double> full;
+  std::vector<double> gfull;
+  int n_eval = 0;
+  // f = +inf for parameters outside the allowed domain or a non-finite likelihood
+  int operator()(const std::vector<double>& x, double& f, std::vector<double>& g) {
+    for (size_t i = 0; i < free.size(); ++i) full[free[i]] = x[i];
+    ++n_eval;
+    int rc = mipwa_set_params(ctx, full.data(), (int)full.size());
+    if (rc == MIPWA_E_INVAL) {
+      f = INFINITY;
+      return MIPWA_OK;
+    }
+    if (rc) return rc;
+    rc = mipwa_eval(ctx, &f, gfull.data());
+    if (rc == MIPWA_E_DOMAIN) {
+      f = INFINITY;
+      return MIPWA_OK;
+    }
+    if (rc) return rc;
+    g.resize(free.size());
+    for (size_t i = 0; i < free.size(); ++i) g[i] = gfull[free[i]];
+    return MIPWA_OK;
+  }
+};
+
+double dot(const std::vector<double>& a, const std::vector<double>& b) {
+  double s = 0.0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
+void matvec(const std::vector<double>& B, const std::vector<double>& x, std::vector<double>& y) {
+  const size_t n = x.size();
+  y.assign(n, 0.0);
+  for (size_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (size_t j = 0; j < n; ++j) s += B[i * n + j] * x[j];
+    y[i] = s;
+  }
+}
+
+// minimiser of the cubic through (a, fa, da) and (b, fb, db), safeguarded to the inner 80% of [a, b]
+double cubic_step(double a, double fa, double da, double b, double fb, double db) {
+  const double lo = std::min(a, b), hi = std::max(a, b), w = hi - lo;
+  double t = 0.5 * (a + b);
+  if (std::isfinite(fb) && std::isfinite(db)) {
+    const double d1 = da + db - 3.0 * (fa - fb) / (a - b);
+    const double disc = d1 * d1 - da * db;
+    if (disc >= 0) {
+      const double d2 = std::copysign(std::sqrt(disc), b - a);
+      const double den = db - da + 2.0 * d2;
+      if (den != 0) t = b - (b - a) * (db + d2 - d1) / den;
+    }
+  }
+  return std::min(std::max(t, lo + 0.1 * w), hi - 0.1 * w);
+}
+
+struct LineResult {
+  bool ok = false;
+  double alpha = 0, f = 0;
+  std::vector<double> x, g;
+};
+
+// strong-Wolfe line search along d from (x0, f0, g0); eps_f is the tolerated noise in f
+int line_search(Objective& obj, const std::vector<double>& x0, double f0, const std::vector<double>& g0,
+                const std::vector<double>& d, double alpha0, double eps_f, LineResult& out) {
+  const double c1 = 1e-4, c2 = 0.9;
+  const double dphi0 = dot(g0, d);
+  const size_t n = x0.size();
+  std::vector<double> x(n), g;
+  auto eval = [&](double a, double& f, double& dphi, std::vector<double>& gx) -> int {
+    for (size_t i = 0; i < n; ++i) x[i] = x0[i] + a * d[i];
+    int rc = obj(x, f, gx);
+    if (rc) return rc;
+    dphi = std::isfinite(f) ? dot(gx, d) : NAN;
+    return MIPWA_OK;
+  };
+  auto accept = [&](double a, double f, const std::vector<double>& gx) {
+    out.ok = true;
+    out.alpha = a;
+    out.f = f;
+    out.x = x;
+    out.g = gx;
+  };
+  auto zoom = [&](double lo, double flo, double dlo, double hi, double fhi, double dhi) -> int {
+    for (int it = 0; it < 30; ++it) {
+      const double a = cubic_step(lo, flo, dlo, hi, fhi, dhi);
+      double f, dp;
+      std::vector<double> gx;
+      int rc = eval(a, f, dp, gx);
+      if (rc) return rc;
+      if (!std::isfinite(f) || f > f0 + c1 * a * dphi0 + eps_f || f >= flo) {
+        hi = a;
+        fhi = f;
+        dhi = dp;
+      } else {
+        if (std::fabs(dp) <= -c2 * dphi0) {
+          accept(a, f, gx);
+          return MIPWA_OK;
+        }
+        if (dp * (hi - lo) >= 0) {
+          hi = lo;
+          fhi = flo;
+          dhi = dlo;
+        }
+        lo = a;
+        flo = f;
+        dlo = dp;
+      }
+      if (std::fabs(hi - lo) < 1e-16 * std::max(1.0, std::fabs(lo))) break;
+    }
+    // no point met both conditions: take the best sufficient-decrease point if it improved f
+    if (lo > 0 && flo < f0) {
+      double f, dp;
+      std::vector<double> gx;
+      int rc = eval(lo, f, dp, gx);
+      if (rc) return rc;
+      accept(lo, f, gx);
+    }
+    return MIPWA_OK;
+  };
+  double a_prev = 0.0, f_prev = f0, d_prev = dphi0;
+  double a = alpha0;
+  for (int it = 0; it < 30; ++it) {
+    double f, dp;
+    std::vector<double> gx;
+    int rc = eval(a, f, dp, gx);
+    if (rc) return rc;
+    if (!std::isfinite(f) || f > f0 + c1 * a * dphi0 + eps_f || (it > 0 && f >= f_prev))
+      return zoom(a_prev, f_prev, d_prev, a, f, dp);
+    if (std::fabs(dp) <= -c2 * dphi0) {
+      accept(a, f, gx);
+      return MIPWA_OK;
+    }
+    if (dp >= 0) return zoom(a, f, dp, a_prev, f_prev, d_prev);
+    a_prev = a;
+    f_prev = f;
+    d_prev = dp;
+    a *= 2.0;
+  }
+  return MIPWA_OK;
+}
+
+bool cholesky_inverse(std::vector<double> A, size_t n, std::vector<double>& inv) {
+  // A = L L^T in place (lower), then inv = L^-T L^-1
+  for (size_t j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (size_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+    if (!(d > 0)) return false;
+    d = std::sqrt(d);
+    A[j * n + j] = d;
+    for (size_t i = j + 1; i < n; ++i) {
+      double s = A[i * n + j];
+      for (size_t k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
+      A[i * n + j] = s / d;
+    }
+  }
+  std::vector<double> Linv(n * n, 0.0);
+  for (size_t i = 0; i < n; ++i) {
+    Linv[i * n + i] = 1.0 / A[i * n + i];
+    for (size_t j = 0; j < i; ++j) {
+      double s = 0.0;
+      for (size_t k = j; k < i; ++k) s -= A[i * n + k] * Linv[k * n + j];
+      Linv[i * n + j] = s / A[i * n + i];
+    }
+  }
+  inv.assign(n * n, 0.0);
+  for (size_t i = 0; i < n; ++i)
+    for (size_t j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (size_t k = i; k < n; ++k) s += Linv[k * n + i] * Linv[k * n + j];
+      inv[i * n + j] = inv[j * n + i] = s;
+    }
+  return true;
+}
+
+}  // namespace
+
+extern "C" int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* theta_inout, double* cov_out,
+                         mipwa_fit_info* info) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!theta_inout) return ctx->fail(MIPWA_E_INVAL, "theta is NULL");
+  const int P = ctx->mh.P, N = ctx->mh.N, R = ctx->mh.R;
+  const double tol = opts && opts->tol_edm > 0 ? opts->tol_edm : 1e-6;
+  const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 1000;
+  const bool want_hess = opts ? opts->hessian != 0 : true;
+  Objective obj{ctx, {}, std::vector<double>(theta_inout, theta_inout + P), std::vector<double>(P), 0};
+  for (int p = 0; p < P; ++p)
+    if (!ctx->fixed[p]) obj.free.push_back(p);
+  const size_t n = obj.free.size();
+  if (n == 0) return ctx->fail(MIPWA_E_INVAL, "every parameter is fixed");
+  std::vector<double> x(n), g, xn, gn;
+  for (size_t i = 0; i < n; ++i) x[i] = theta_inout[obj.free[i]];
+  double f = 0.0;
+  int rc = obj(x, f, g);
+  if (rc) return rc;
+  if (!std::isfinite(f)) return ctx->fail(MIPWA_E_DOMAIN, "-2 ln L is not finite at the start point");
+  // FP32 streams leave ~1e-11 relative noise in f; allow it in the sufficient-decrease test
+  const double eps_rel = ctx->fp64 ? 1e-13 : 1e-10;
+  std::vector<double> B(n * n, 0.0);
+  const double gmax = std::max(1e-300, std::fabs(*std::max_element(g.begin(), g.end(), [](double a, double b) {
+    return std::fabs(a) < std::fabs(b);
+  })));
+  const double b0 = 0.1 / gmax;  // first step moves the steepest parameter by about 0.1
+  for (size_t i = 0; i < n; ++i) B[i * n + i] = b0;
+  std::vector<double> d, Bg;
+  int iter = 0, status = MIPWA_E_NOCONV;
+  double edm = 0.0;
+  bool scaled = false;
+  for (; iter < max_iter; ++iter) {
+    matvec(B, g, Bg);
+    edm = 0.5 * dot(g, Bg);
+    if (edm < tol) {
+      status = MIPWA_OK;
+      break;
+    }
+    d.resize(n);
+    for (size_t i = 0; i < n; ++i) d[i] = -Bg[i];
+    if (dot(g, d) >= 0) {  // lost positive definiteness: restart from a scaled identity
+      std::fill(B.begin(), B.end(), 0.0);
+      for (size_t i = 0; i < n; ++i) B[i * n + i] = b0, d[i] = -b0 * g[i];
+    }
+    LineResult lr;
+    rc = line_search(obj, x, f, g, d, 1.0, eps_rel * std::fabs(f), lr);
+    if (rc) return rc;
+    if (!lr.ok) {
+      // retry once along steepest descent before giving up
+      std::fill(B.begin(), B.end(), 0.0);
+      for (size_t i = 0; i < n; ++i) B[i * n + i] = b0, d[i] = -b0 * g[i];
+      rc = line_search(obj, x, f, g, d, 1.0, eps_rel * std::fabs(f), lr);
+      if (rc) return rc;
+      if (!lr.ok) break;
+    }
+    std::vector<double> s(n), y(n);
+    for (size_t i = 0; i < n; ++i) {
+      s[i] = lr.x[i] - x[i];
+      y[i] = lr.g[i] - g[i];
+    }
+    const double sy = dot(s, y);
+    if (!scaled && sy > 0) {
+      const double sc = sy / dot(y, y);
+      std::fill(B.begin(), B.end(), 0.0);
+      for (size_t i = 0; i < n; ++i) B[i * n + i] = sc;
+      scaled = true;
+    }
+    if (sy > 1e-12 * std::sqrt(dot(s, s) * dot(y, y))) {
+      const double rho = 1.0 / sy;
+      std::vector<double> By;
+      matvec(B, y, By);
+      const double yBy = dot(y, By);
+      // B + rho^2 (y^T B y) s s^T + rho s s^T - rho (B y s^T + s y^T B)
+      for (size_t i = 0; i < n; ++i)
+        for (size_t j = 0; j < n; ++j)
+          B[i * n + j] += (rho * rho * yBy + rho) * s[i] * s[j] - rho * (By[i] * s[j] + s[i] * By[j]);
+    }
+    x = lr.x;
+    f = lr.f;
+    g = lr.g;
+  }
+  if (iter >= max_iter) {
+    matvec(B, g, Bg);
+    edm = 0.5 * dot(g, Bg);
+    if (edm < tol) status = MIPWA_OK;
+  }
+  // covariance
+  std::vector<double> V(n * n);
+  for (size_t i = 0; i < n * n; ++i) V[i] = 2.0 * B[i];
+  if (want_hess) {
+    std::vector<double> H(n * n), xp, gp, gm;
+    double fp, fm;
+    for (size_t i = 0; i < n; ++i) {
+      const double h = 1e-4 * std::max(1.0, std::fabs(x[i]));
+      xp = x;
+      xp[i] += h;
+      rc = obj(xp, fp, gp);
+      if (rc) return rc;
+      xp[i] = x[i] - h;
+      rc = obj(xp, fm, gm);
+      if (rc) return rc;
+      for (size_t j = 0; j < n; ++j) H[j * n + i] = (gp[j] - gm[j]) / (2.0 * h);
+    }
+    for (size_t i = 0; i < n; ++i)
+      for (size_t j = 0; j < i; ++j) H[i * n + j] = H[j * n + i] = 0.5 * (H[i * n + j] + H[j * n + i]);
+    std::vector<double> Hinv;
+    if (cholesky_inverse(H, n, Hinv)) {
+      for (size_t i = 0; i < n * n; ++i) V[i] = 2.0 * Hinv[i];
+      matvec(Hinv, g, Bg);
+      edm = 0.5 * dot(g, Bg);
+    }
+  }
+  // restore the evaluation at the minimum (the Hessian loop moved the context's parameters)
+  std::vector<double> gfinal;
+  rc = obj(x, f, gfinal);
+  if (rc) return rc;
+  for (size_t i = 0; i < n; ++i) theta_inout[obj.free[i]] = x[i];
+  // fold (magnitude, phase) pairs: magnitude >= 0, phase in (-pi, pi]
+  for (int k = 0; k < N + R; ++k) {
+    double a = theta_inout[2 * k], p = theta_inout[2 * k + 1];
+    if (a < 0) {
+      a = -a;
+      p += M_PI;
+    }
+    p = M_PI - std::fmod(std::fmod(M_PI - p, 2.0 * M_PI) + 2.0 * M_PI, 2.0 * M_PI);
+    theta_inout[2 * k] = a;
+    theta_inout[2 * k + 1] = p;
+  }
+  (void)mipwa_set_params(ctx, theta_inout, P);
+  if (cov_out) {
+    std::memset(cov_out, 0, sizeof(double) * P * P);
+    for (size_t i = 0; i < n; ++i)
+      for (size_t j = 0; j < n; ++j) cov_out[(size_t)obj.free[i] * P + obj.free[j]] = V[i * n + j];
+  }
+  if (info) {
+    info->nll = f;
+    info->edm = edm;
+    info->n_iter = iter;
+    info->n_eval = obj.n_eval;
+    info->status = status;
+  }
+  if (status != MIPWA_OK) return ctx->fail(MIPWA_E_NOCONV, "EDM above tolerance after max_iter iterations or a failed line search");
+  return MIPWA_OK;
+}

@@ -1,0 +1,126 @@
+// Host-side FP64 pieces of the library: spline setup, resonance constants, point loading, and the
+// context that owns every device buffer.  Internal; the public boundary is include/mipwa.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "mipwa.h"
+
+namespace mipwa {
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, n ? n : 16);
+    if (e == hipSuccess) bytes = n;
+    else p = nullptr;
+    return e;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Pinned host allocation.
+struct HostBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipHostMalloc(&p, n ? n : 16, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = n;
+    else p = nullptr;
+    return e;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// The static part of a model: kinematics, knots, resonances and the factorised spline operator.
+struct ModelHost {
+  double M = 0, m1 = 0, m2 = 0, m3 = 0, rD = 0;
+  std::vector<double> knots, h;  // N knots, N-1 interval lengths
+  std::vector<mipwa_res> res;
+  int N = 0, R = 0, P = 0;
+  std::vector<double> KT;        // N x N, KT[k*N+i] = dM_i/dz_k (natural spline)
+  std::vector<double> th_c;      // Thomas factors (interior unknowns)
+  std::vector<double> th_d;
+  Kin<double> kin64{};
+  Kin<float> kin32{};
+
+  int init(const mipwa_model* m, std::string& err);
+  double smin() const { return (m1 + m2) * (m1 + m2); }
+  double smax() const { return (M - m3) * (M - m3); }
+  // second derivatives M (complex, as re/im arrays) from knot values z
+  void second_derivs(const double* zr, const double* zi, double* Mr, double* Mi) const;
+  // spline polynomial coefficients per interval: 8 doubles (P0..P3 re/im) per interval
+  void poly_table(const double* theta, double* out) const;
+  // per-resonance constants (kResWords doubles each) at the given masses/widths in theta
+  void res_table(const double* theta, double* out) const;
+  int interval(double s) const;
+  bool inside(double s12, double s13, double tol) const;
+  int check_theta(const double* theta, std::string& err) const;
+};
+
+struct PointSet {
+  long long n = 0;
+  int n_tiles = 0;
+  DevBuf tt, ss, w, wplain, cache, tiles;
+  double c_eps = 0.0;       // -2 sum ln eff (events)
+  bool loaded = false;
+};
+
+// Load host points into a point set: validate, swap each pair to s12 <= s13, locate the spline
+// cells, stable counting sort by cell, cut tiles, compute local coordinates in FP64, upload.
+// eps_dev_fn: when no eff array is given and a table is set, eff is looked up on the device.
+struct EffTable {
+  std::vector<float> tab;
+  int nx = 0, ny = 0;
+  double lo = 0, hi = 0;
+  DevBuf d;
+  bool set() const { return nx > 0; }
+};
+
+int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, const double* s13, const double* w,
+                const double* eff, long long n, const EffTable& et, hipStream_t st, PointSet& ps,
+                std::string& err);
+
+}  // namespace mipwa

@@ -1,0 +1,834 @@
+// gfx950 kernels of the MIPWA likelihood.
+//
+// What is computed (see include/mipwa.h for the method and its readings):
+//   A(s12,s13) = S(s12) + S(s13) + sum_r c_r R_r(s12,s13)            (Sec. 2 Eq. 1, Sec. 4 symmetrisation)
+//   data:  sum ln|A|^2 and the adjoint seed g = -4 A/|A|^2
+//   norm:  sum w eff |A|^2 and the seed g = 4 w eff A (scaled by n/I in the finish)
+//   adjoint: per spline interval j and power m, sum g t^m; per resonance sum g conj(R_r) and, when
+//   masses/widths float, sum g conj(dR_r/dm), sum g conj(dR_r/dGamma).
+//
+// Layout: points are sorted at load time by spline cell (j12, j13) and cut into tiles of at most kTile
+// points of one cell, so the interval indices and the spline polynomials are wave-uniform (scalar
+// registers).  Point streams are SoA pairs (t12,t13), (s12,s13), w, and one complex plane per
+// resonance, read coalesced.  Each wave owns a contiguous range of tiles, keeps its adjoint partials
+// in registers while the cell does not change, and folds them into a wave-private LDS histogram of
+// spline intervals when it does.  Blocks write fixed-size FP64 records; a second kernel reduces them
+// in a fixed order (bitwise reproducible) and runs the FP64 finish.
+#include <hip/hip_runtime.h>
+
+#include "engine.h"
+
+namespace mipwa {
+
+template <typename Real>
+struct Ops;
+
+template <>
+struct Ops<float> {
+  using V2 = float2;
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+  static __device__ __forceinline__ float log(float x) { return __logf(x); }
+};
+
+template <>
+struct Ops<double> {
+  using V2 = double2;
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double rsqrt(double x) { return ::rsqrt(x); }
+  static __device__ __forceinline__ double log(double x) { return ::log(x); }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Breit-Wigner amplitudes of all R resonances for one pairing: x is the resonant h-h+ invariant, y
+// the other one (Sec. 2: relativistic Breit-Wigner times a real angular factor; the readings are the
+// running width with Blatt-Weisskopf factors and Zemach tensors).  With the per-resonance constants
+// kappa = sqrt(N_L(z_qr) N_L(z_pr)) and delta = Gamma_r m_r^2 N_L(z_qr) / q_r^(2L+1):
+//   BW = kappa f(x) T_L(x,y) / (m_r^2 - x - i delta u(x)),
+//   f = 1/sqrt(N_L(rho^2 q^2) N_L(rD^2 p^2)),  u = q^(2L+1) / (sqrt(x) N_L(rho^2 q^2)),
+// which is B_L(q) B_L(p) T_L / (m_r^2 - x - i m_r Gamma(x)).  With DER it also adds
+//   dBW/dm = BW (dln kappa/dm - (2 m_r - i ddelta/dm u) / D),   dBW/dGamma = BW i (ddelta/dGamma) u / D.
+template <typename Real, int R, bool DER>
+__device__ __forceinline__ void bw_pairing(const Kin<Real>& k, const Real* __restrict__ res, Real x, Real y,
+                                           Real* br, Real* bi, Real* mr, Real* mi, Real* gr, Real* gi) {
+  using O = Ops<Real>;
+  const Real ix = O::rcp(x);
+  Real q2 = (x - k.thr_hi) * (x - k.thr_lo) * (Real(0.25) * ix);
+  Real p2 = (x - k.pb_hi) * (x - k.pb_lo) * (Real(0.25) * ix);
+  q2 = q2 > Real(0) ? q2 : Real(0);
+  p2 = p2 > Real(0) ? p2 : Real(0);
+  const Real sx = O::sqrt(x);
+  const Real q = O::sqrt(q2);
+  const Real t1 = k.sum - x - y - y + k.t1corr * ix;
+  const Real t2 = t1 * t1 - (x - k.t2a + k.t2b * ix) * (x - k.t2c + k.t2d * ix) * Real(1.0 / 3.0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const Real* c = res + r * kResWords;
+    const Real m2 = c[0], kappa = c[1], delta = c[2], rho2 = c[3];
+    const int L = (int)c[4];
+    const Real zq = rho2 * q2, zp = k.rD2 * p2;
+    Real nq, np, qp, T;
+    if (L == 1) {
+      nq = Real(1) + zq;
+      np = Real(1) + zp;
+      qp = q2 * q;
+      T = t1;
+    } else if (L == 2) {
+      nq = (zq + Real(3)) * zq + Real(9);
+      np = (zp + Real(3)) * zp + Real(9);
+      qp = q2 * q2 * q;
+      T = t2;
+    } else {
+      nq = Real(1);
+      np = Real(1);
+      qp = q;
+      T = Real(1);
+    }
+    const Real f = O::rsqrt(nq * np);
+    const Real u = qp * O::rcp(sx * nq);
+    const Real dre = m2 - x, dim = -delta * u;
+    const Real idd = O::rcp(dre * dre + dim * dim);
+    const Real num = kappa * f * T * idd;
+    const Real vr = num * dre, vi = -num * dim;
+    br[r] += vr;
+    bi[r] += vi;
+    if constexpr (DER) {
+      const Real ire = dre * idd, iim = -dim * idd;  // 1/D
+      const Real mass = c[5], dlk = c[6], ddm = c[7], ddg = c[8];
+      const Real zr = Real(2) * mass * ire + ddm * u * iim;
+      const Real zi = Real(2) * mass * iim - ddm * u * ire;
+      const Real fr = dlk - zr, fi = -zi;
+      mr[r] += vr * fr - vi * fi;
+      mi[r] += vr * fi + vi * fr;
+      const Real hr = -ddg * u * iim, hi = ddg * u * ire;
+      gr[r] += vr * hr - vi * hi;
+      gi[r] += vr * hi + vi * hr;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// K1: symmetrised resonance amplitudes R_r = BW_r(s12,s13) + BW_r(s13,s12) at every point.
+
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_cache(Segment sg, const Real* __restrict__ table, Kin<Real> kin) {
+  using V2 = typename Ops<Real>::V2;
+  constexpr int R1 = R > 0 ? R : 1;
+  const Real* res = table + 8 * sg.nint + 2 * R;
+  const V2* __restrict__ ss = (const V2*)sg.ss;
+  V2* __restrict__ cache = (V2*)sg.cache;
+  const long long n = sg.n;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const V2 s = ss[p];
+    Real br[R1] = {}, bi[R1] = {};
+    bw_pairing<Real, R, false>(kin, res, s.x, s.y, br, bi, nullptr, nullptr, nullptr, nullptr);
+    bw_pairing<Real, R, false>(kin, res, s.y, s.x, br, bi, nullptr, nullptr, nullptr, nullptr);
+#pragma unroll
+    for (int r = 0; r < R; ++r) cache[(long long)r * n + p] = V2{br[r], bi[r]};
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// K2: fused forward + adjoint over the tiles of one segment, persistent waves.
+
+template <typename Real, int R, bool OTF, int KIND>
+__device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& kin, double* bins,
+                                            double* scal, int wave, int lane, int waves) {
+  using O = Ops<Real>;
+  using V2 = typename O::V2;
+  constexpr int R1 = R > 0 ? R : 1;
+  constexpr int IT = kTile / 64;
+  const Real* __restrict__ tab = (const Real*)sg.table;
+  const Real* __restrict__ cv = tab + 8 * sg.nint;
+  const Real* __restrict__ res = cv + 2 * R;
+  Real cre[R1], cim[R1];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    cre[r] = cv[2 * r];
+    cim[r] = cv[2 * r + 1];
+  }
+  const V2* __restrict__ tt = (const V2*)sg.tt;
+  const V2* __restrict__ ss = (const V2*)sg.ss;
+  const Real* __restrict__ ww = (const Real*)sg.w;
+  const V2* __restrict__ cache = (const V2*)sg.cache;
+  const long long n = sg.n;
+
+  const long long nw = (long long)sg.n_blocks * waves;
+  const long long gw = (long long)(blockIdx.x - sg.block0) * waves + wave;
+  const int t0 = (int)(sg.n_tiles * gw / nw);
+  const int t1 = (int)(sg.n_tiles * (gw + 1) / nw);
+
+  double q12[8], q13[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) q12[m] = q13[m] = 0.0;
+  double acc = 0.0;
+  double agc[2 * R1], ahm[2 * R1], ahg[2 * R1];
+#pragma unroll
+  for (int r = 0; r < 2 * R1; ++r) agc[r] = ahm[r] = ahg[r] = 0.0;
+
+  int cj12 = -1, cj13 = -1;
+  Real p12[8], p13[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) p12[m] = p13[m] = Real(0);
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const double a = wave_sum(q12[m]);
+      const double b = wave_sum(q13[m]);
+      q12[m] = 0.0;
+      q13[m] = 0.0;
+      if (lane == 0) {
+        bins[8 * cj12 + m] += a;
+        bins[8 * cj13 + m] += b;
+      }
+    }
+  };
+
+  for (int ti = t0; ti < t1; ++ti) {
+    const Tile td = sg.tiles[ti];
+    if (td.j12 != cj12 || td.j13 != cj13) {
+      if (cj12 >= 0) flush();
+      cj12 = td.j12;
+      cj13 = td.j13;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        p12[m] = tab[8 * cj12 + m];
+        p13[m] = tab[8 * cj13 + m];
+      }
+    }
+    // Loads of IB points per lane are issued before any of them is used (memory-level
+    // parallelism for the streaming variant); the on-the-fly variant is ALU-bound and takes one
+    // point at a time to stay within the register file.  Lanes past the tile end re-read its last
+    // point and contribute zero.
+    constexpr int IB = OTF ? 1 : IT;
+#pragma unroll 1
+    for (int ib = 0; ib < IT; ib += IB) {
+      V2 tv[IB];
+      V2 rv[IB][R1];
+      V2 sv[IB];
+      Real wv[IB];
+      bool valid[IB];
+#pragma unroll
+      for (int k = 0; k < IB; ++k) {
+        const int i = (ib + k) * 64 + lane;
+        valid[k] = i < td.count;
+        const long long p = (long long)td.start + (valid[k] ? i : td.count - 1);
+        tv[k] = tt[p];
+        if constexpr (OTF) {
+          sv[k] = ss[p];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) rv[k][r] = cache[(long long)r * n + p];
+        }
+        if constexpr (KIND == 1) wv[k] = ww[p];
+      }
+#pragma unroll
+      for (int k = 0; k < IB; ++k) {
+        const Real x12 = tv[k].x, x13 = tv[k].y;
+        Real ar = p12[0] + x12 * (p12[2] + x12 * (p12[4] + x12 * p12[6]));
+        Real ai = p12[1] + x12 * (p12[3] + x12 * (p12[5] + x12 * p12[7]));
+        ar += p13[0] + x13 * (p13[2] + x13 * (p13[4] + x13 * p13[6]));
+        ai += p13[1] + x13 * (p13[3] + x13 * (p13[5] + x13 * p13[7]));
+        Real rr[R1], ri[R1], dmr[R1], dmi[R1], dgr[R1], dgi[R1];
+        if constexpr (OTF) {
+#pragma unroll
+          for (int r = 0; r < R1; ++r) rr[r] = ri[r] = dmr[r] = dmi[r] = dgr[r] = dgi[r] = Real(0);
+          bw_pairing<Real, R, true>(kin, res, sv[k].x, sv[k].y, rr, ri, dmr, dmi, dgr, dgi);
+          bw_pairing<Real, R, true>(kin, res, sv[k].y, sv[k].x, rr, ri, dmr, dmi, dgr, dgi);
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            rr[r] = rv[k][r].x;
+            ri[r] = rv[k][r].y;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ar += cre[r] * rr[r] - cim[r] * ri[r];
+          ai += cre[r] * ri[r] + cim[r] * rr[r];
+        }
+        const Real a2 = ar * ar + ai * ai;
+        Real sr, si;
+        if constexpr (KIND == 0) {
+          const Real l = O::log(a2);
+          acc += valid[k] ? (double)l : 0.0;
+          const Real s = valid[k] ? Real(-4) * O::rcp(a2) : Real(0);
+          sr = s * ar;
+          si = s * ai;
+        } else {
+          const Real w = valid[k] ? wv[k] : Real(0);
+          acc += (double)w * (double)a2;
+          sr = Real(4) * w * ar;
+          si = Real(4) * w * ai;
+        }
+        const double g_r = sr, g_i = si;
+        {
+          const double x = x12, x2 = x * x, x3 = x2 * x;
+          q12[0] += g_r;
+          q12[1] += g_i;
+          q12[2] += g_r * x;
+          q12[3] += g_i * x;
+          q12[4] += g_r * x2;
+          q12[5] += g_i * x2;
+          q12[6] += g_r * x3;
+          q12[7] += g_i * x3;
+        }
+        {
+          const double x = x13, x2 = x * x, x3 = x2 * x;
+          q13[0] += g_r;
+          q13[1] += g_i;
+          q13[2] += g_r * x;
+          q13[3] += g_i * x;
+          q13[4] += g_r * x2;
+          q13[5] += g_i * x2;
+          q13[6] += g_r * x3;
+          q13[7] += g_i * x3;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double Rr = rr[r], Ri = ri[r];
+          agc[2 * r] += g_r * Rr + g_i * Ri;
+          agc[2 * r + 1] += g_i * Rr - g_r * Ri;
+          if constexpr (OTF) {
+            const double Mr = dmr[r], Mi = dmi[r], Gr = dgr[r], Gi = dgi[r];
+            ahm[2 * r] += g_r * Mr + g_i * Mi;
+            ahm[2 * r + 1] += g_i * Mr - g_r * Mi;
+            ahg[2 * r] += g_r * Gr + g_i * Gi;
+            ahg[2 * r + 1] += g_i * Gr - g_r * Gi;
+          }
+        }
+      }
+    }
+  }
+  if (cj12 >= 0) flush();
+
+  const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
+  double* my = scal + wave * nsc;
+  {
+    const double v = wave_sum(acc);
+    if (lane == 0) my[0] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < 2 * R; ++r) {
+    const double v = wave_sum(agc[r]);
+    if (lane == 0) my[1 + r] = v;
+    if constexpr (OTF) {
+      const double a = wave_sum(ahm[r]);
+      const double b = wave_sum(ahg[r]);
+      if (lane == 0) {
+        my[1 + 2 * R + r] = a;
+        my[1 + 4 * R + r] = b;
+      }
+    }
+  }
+}
+
+template <typename Real, int R, bool OTF>
+__global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, const int* __restrict__ block_seg,
+                                              Kin<Real> kin, int max_nint) {
+  extern __shared__ double lds[];
+  const int waves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const Segment sg = segs[block_seg[blockIdx.x]];
+  const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
+  const int stride = 8 * max_nint;
+  double* bins = lds;
+  double* scal = lds + waves * stride;
+  for (int i = threadIdx.x; i < waves * stride + waves * nsc; i += blockDim.x) lds[i] = 0.0;
+  __syncthreads();
+  if (sg.kind == 0)
+    run_segment<Real, R, OTF, 0>(sg, kin, bins + wave * stride, scal, wave, lane, waves);
+  else
+    run_segment<Real, R, OTF, 1>(sg, kin, bins + wave * stride, scal, wave, lane, waves);
+  __syncthreads();
+  double* rec = sg.records + (long long)(blockIdx.x - sg.block0) * sg.rs;
+  const int nb = 8 * sg.nint;
+  for (int f = threadIdx.x; f < nb + nsc; f += blockDim.x) {
+    double s = 0.0;
+    if (f < nb) {
+      for (int w = 0; w < waves; ++w) s += bins[w * stride + f];
+    } else {
+      for (int w = 0; w < waves; ++w) s += scal[w * nsc + (f - nb)];
+    }
+    rec[f] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// K3: fixed-order reduction of the block records, then the FP64 finish (last block per job):
+//   -2 ln L = -2 S_data + C_eps + 2 n ln I,  scale = n / I,
+//   spline-polynomial partials -> knot values z and second derivatives M -> z through M = K z,
+//   then the chain rule to (a_k, phi_k), (|c_r|, arg c_r), (m_r, Gamma_r).
+
+__device__ void finish_job(const Job& jb) {
+  const int N = jb.N, nint = N - 1, R = jb.R, P = 2 * N + 4 * R;
+  const double* fd = jb.fin;
+  const double* fn = jb.fin + jb.rs;
+  const int s0 = 8 * nint;
+  const double I = fn[s0];
+  const double scale = jb.n_ev / I;
+  const double* th = jb.tab64;
+  const double* KT = th + P;
+  const double* h = KT + N * N;
+  __shared__ double gy[2 * kMaxKnots], gm[2 * kMaxKnots];
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    double yr = 0, yi = 0, mr = 0, mi = 0;
+    if (k < nint) {
+      const double* a = fd + 8 * k;
+      const double* b = fn + 8 * k;
+      const double q0r = a[0] + scale * b[0], q0i = a[1] + scale * b[1];
+      const double q1r = a[2] + scale * b[2], q1i = a[3] + scale * b[3];
+      const double q2r = a[4] + scale * b[4], q2i = a[5] + scale * b[5];
+      const double q3r = a[6] + scale * b[6], q3i = a[7] + scale * b[7];
+      const double c = h[k] * h[k] / 6.0;
+      yr += q0r - q1r;
+      yi += q0i - q1i;
+      mr += c * (-2.0 * q1r + 3.0 * q2r - q3r);
+      mi += c * (-2.0 * q1i + 3.0 * q2i - q3i);
+    }
+    if (k > 0) {
+      const int j = k - 1;
+      const double* a = fd + 8 * j;
+      const double* b = fn + 8 * j;
+      const double q1r = a[2] + scale * b[2], q1i = a[3] + scale * b[3];
+      const double q3r = a[6] + scale * b[6], q3i = a[7] + scale * b[7];
+      const double c = h[j] * h[j] / 6.0;
+      yr += q1r;
+      yi += q1i;
+      mr += c * (q3r - q1r);
+      mi += c * (q3i - q1i);
+    }
+    gy[2 * k] = yr;
+    gy[2 * k + 1] = yi;
+    gm[2 * k] = mr;
+    gm[2 * k + 1] = mi;
+  }
+  __syncthreads();
+  double* out = jb.out;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    double yr = gy[2 * k], yi = gy[2 * k + 1];
+    for (int i = 0; i < N; ++i) {
+      const double kt = KT[k * N + i];
+      yr += kt * gm[2 * i];
+      yi += kt * gm[2 * i + 1];
+    }
+    const double a = th[2 * k], ph = th[2 * k + 1];
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    out[1 + 2 * k] = yr * cs + yi * sn;
+    out[2 + 2 * k] = a * (-yr * sn + yi * cs);
+  }
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    const double gr = fd[s0 + 1 + 2 * r] + scale * fn[s0 + 1 + 2 * r];
+    const double gi = fd[s0 + 2 + 2 * r] + scale * fn[s0 + 2 + 2 * r];
+    const double cm = th[2 * N + 2 * r], ca = th[2 * N + 2 * r + 1];
+    double sn, cs;
+    sincos(ca, &sn, &cs);
+    out[1 + 2 * N + 2 * r] = gr * cs + gi * sn;
+    out[2 + 2 * N + 2 * r] = cm * (-gr * sn + gi * cs);
+    double dm = 0.0, dg = 0.0;
+    if (jb.otf) {
+      const int om = s0 + 1 + 2 * R + 2 * r, og = s0 + 1 + 4 * R + 2 * r;
+      const double hmr = fd[om] + scale * fn[om], hmi = fd[om + 1] + scale * fn[om + 1];
+      const double hgr = fd[og] + scale * fn[og], hgi = fd[og + 1] + scale * fn[og + 1];
+      const double cr = cm * cs, ci = cm * sn;
+      dm = cr * hmr + ci * hmi;
+      dg = cr * hgr + ci * hgi;
+    }
+    out[1 + 2 * N + 2 * R + 2 * r] = dm;
+    out[2 + 2 * N + 2 * R + 2 * r] = dg;
+  }
+  if (threadIdx.x == 0) out[0] = -2.0 * fd[s0] + jb.c_eps + 2.0 * jb.n_ev * log(I);
+}
+
+__global__ __launch_bounds__(256) void k_finish(const Job* __restrict__ jobs) {
+  const Job jb = jobs[blockIdx.y];
+  if ((int)blockIdx.x >= jb.n_chunks) return;
+  __shared__ double part[4][64];
+  __shared__ int is_last;
+  const int lane = threadIdx.x & 63, prt = threadIdx.x >> 6;
+  const int f = blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (f < 2 * jb.rs) {
+    const bool isn = f >= jb.rs;
+    const int ff = isn ? f - jb.rs : f;
+    const double* rec = isn ? jb.rec_n : jb.rec_d;
+    const int nb = isn ? jb.nb_n : jb.nb_d;
+    for (int b = prt; b < nb; b += 4) acc += rec[(long long)b * jb.rs + ff];
+  }
+  part[prt][lane] = acc;
+  __syncthreads();
+  if (prt == 0 && f < 2 * jb.rs)
+    jb.fin[f] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(jb.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = prev == (unsigned)(jb.n_chunks - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  finish_job(jb);
+  if (threadIdx.x == 0) __hip_atomic_store(jb.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Component integrals I_jk = sum_p w_p A_j A_k^* over the normalisation points (Eq. 1 components).
+
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_integrals(Segment sg, const Real* __restrict__ wsel,
+                                                   double* __restrict__ records) {
+  using V2 = typename Ops<Real>::V2;
+  constexpr int K = R + 1;
+  __shared__ double part[4][2 * K * K];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const Real* __restrict__ tab = (const Real*)sg.table;
+  const V2* __restrict__ tt = (const V2*)sg.tt;
+  const V2* __restrict__ cache = (const V2*)sg.cache;
+  double acc[2 * K * K];
+#pragma unroll
+  for (int i = 0; i < 2 * K * K; ++i) acc[i] = 0.0;
+  for (int ti = blockIdx.x * 4 + wave; ti < sg.n_tiles; ti += gridDim.x * 4) {
+    const Tile td = sg.tiles[ti];
+    const Real* p12 = tab + 8 * td.j12;
+    const Real* p13 = tab + 8 * td.j13;
+    for (int i = lane; i < td.count; i += 64) {
+      const long long p = (long long)td.start + i;
+      const Real x12 = tt[p].x, x13 = tt[p].y;
+      double cr[K], ci[K];
+      cr[0] = (double)(p12[0] + x12 * (p12[2] + x12 * (p12[4] + x12 * p12[6]))) +
+              (double)(p13[0] + x13 * (p13[2] + x13 * (p13[4] + x13 * p13[6])));
+      ci[0] = (double)(p12[1] + x12 * (p12[3] + x12 * (p12[5] + x12 * p12[7]))) +
+              (double)(p13[1] + x13 * (p13[3] + x13 * (p13[5] + x13 * p13[7])));
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const V2 v = cache[(long long)r * sg.n + p];
+        cr[r + 1] = v.x;
+        ci[r + 1] = v.y;
+      }
+      const double w = wsel[p];
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          acc[2 * (j * K + k)] += w * (cr[j] * cr[k] + ci[j] * ci[k]);
+          acc[2 * (j * K + k) + 1] += w * (ci[j] * cr[k] - cr[j] * ci[k]);
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2 * K * K; ++i) {
+    const double v = wave_sum(acc[i]);
+    if (lane == 0) part[wave][i] = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * K * K; i += blockDim.x)
+    records[(long long)blockIdx.x * 2 * K * K + i] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+}
+
+__global__ __launch_bounds__(256) void k_sum_records(const double* __restrict__ rec, int nrec, int rs,
+                                                     double* __restrict__ out) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, prt = threadIdx.x >> 6;
+  const int f = blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (f < rs)
+    for (int b = prt; b < nrec; b += 4) acc += rec[(long long)b * rs + f];
+  part[prt][lane] = acc;
+  __syncthreads();
+  if (prt == 0 && f < rs) out[f] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Efficiency table lookup: bilinear between bin centres, constant beyond the outermost centres; the
+// bin index is decided in FP64.
+
+__device__ __forceinline__ double eff_lookup(const float* __restrict__ tab, int nx, int ny, double lo, double hi,
+                                             double s12, double s13) {
+  const double dx = (hi - lo) / nx, dy = (hi - lo) / ny;
+  double ux = (s12 - lo) / dx - 0.5, uy = (s13 - lo) / dy - 0.5;
+  double fx = floor(ux), fy = floor(uy);
+  fx = fx < 0.0 ? 0.0 : (fx > nx - 2 ? nx - 2 : fx);
+  fy = fy < 0.0 ? 0.0 : (fy > ny - 2 ? ny - 2 : fy);
+  const int i = (int)fx, j = (int)fy;
+  double tx = ux - i, ty = uy - j;
+  tx = tx < 0.0 ? 0.0 : (tx > 1.0 ? 1.0 : tx);
+  ty = ty < 0.0 ? 0.0 : (ty > 1.0 ? 1.0 : ty);
+  const double a = tab[i * ny + j], b = tab[(i + 1) * ny + j], c = tab[i * ny + j + 1], d = tab[(i + 1) * ny + j + 1];
+  return (1.0 - tx) * (1.0 - ty) * a + tx * (1.0 - ty) * b + (1.0 - tx) * ty * c + tx * ty * d;
+}
+
+__global__ __launch_bounds__(256) void k_eff(const double* __restrict__ s12, const double* __restrict__ s13, long long n,
+                                             const float* __restrict__ tab, int nx, int ny, double lo, double hi,
+                                             double* __restrict__ eps) {
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x)
+    eps[p] = eff_lookup(tab, nx, ny, lo, hi, s12[p], s13[p]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Toy generation (FP64): Philox4x32-10 candidates, region test, accept-reject on |A|^2 eff.
+
+struct U4 {
+  unsigned x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const unsigned long long p0 = (unsigned long long)0xD2511F53u * c.x;
+    const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
+    const unsigned hi0 = (unsigned)(p0 >> 32), lo0 = (unsigned)p0;
+    const unsigned hi1 = (unsigned)(p1 >> 32), lo1 = (unsigned)p1;
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+__device__ __forceinline__ double unit53(unsigned a, unsigned b) {
+  return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ double map_box(double lo, double span, double u) {
+#pragma clang fp contract(off)
+  const double t = span * u;
+  return lo + t;
+}
+
+__device__ __forceinline__ bool inside_dalitz(const GenArgs& g, double s12, double s13) {
+  const double lo = (g.m1 + g.m2) * (g.m1 + g.m2), hi = (g.M - g.m3) * (g.M - g.m3);
+  if (!(s12 >= lo && s12 <= hi)) return false;
+  const double rs = sqrt(s12);
+  const double e1 = (s12 - g.m2 * g.m2 + g.m1 * g.m1) / (2.0 * rs);
+  const double e3 = (g.M * g.M - s12 - g.m3 * g.m3) / (2.0 * rs);
+  const double p1 = sqrt(fmax(e1 * e1 - g.m1 * g.m1, 0.0));
+  const double p3 = sqrt(fmax(e3 * e3 - g.m3 * g.m3, 0.0));
+  const double es = (e1 + e3) * (e1 + e3);
+  return s13 >= es - (p1 + p3) * (p1 + p3) && s13 <= es - (p1 - p3) * (p1 - p3);
+}
+
+__device__ __forceinline__ void spline_at(const GenArgs& g, double s, double& re, double& im) {
+  int lo = 0, hi = g.N;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (g.knots[mid] <= s)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  int j = lo - 1;
+  j = j < 0 ? 0 : (j > g.N - 2 ? g.N - 2 : j);
+  const double t = (s - g.knots[j]) / (g.knots[j + 1] - g.knots[j]);
+  const double* p = g.poly + 8 * j;
+  re += p[0] + t * (p[2] + t * (p[4] + t * p[6]));
+  im += p[1] + t * (p[3] + t * (p[5] + t * p[7]));
+}
+
+template <int R>
+__global__ __launch_bounds__(kGenBlock) void k_generate(GenArgs g, Kin<double> kin, long long first, int count,
+                                                        double* __restrict__ o12, double* __restrict__ o13,
+                                                        double* __restrict__ of, unsigned char* __restrict__ oflag,
+                                                        int* __restrict__ block_counts, int* __restrict__ exceeded) {
+  constexpr int R1 = R > 0 ? R : 1;
+  const int i = blockIdx.x * kGenBlock + threadIdx.x;
+  int flag = 0;
+  if (i < count) {
+    const unsigned long long idx = (unsigned long long)(first + i);
+    const unsigned k0 = (unsigned)g.seed, k1 = (unsigned)(g.seed >> 32);
+    const U4 a = philox4x32_10(U4{(unsigned)idx, (unsigned)(idx >> 32), 0u, 0u}, k0, k1);
+    const U4 b = philox4x32_10(U4{(unsigned)idx, (unsigned)(idx >> 32), 1u, 0u}, k0, k1);
+    const double s12 = map_box(g.smin, g.span, unit53(a.x, a.y));
+    const double s13 = map_box(g.smin, g.span, unit53(a.z, a.w));
+    const double v = unit53(b.x, b.y);
+    const bool in = inside_dalitz(g, s12, s13);
+    double f = 0.0;
+    if (in) {
+      double ar = 0.0, ai = 0.0;
+      spline_at(g, s12, ar, ai);
+      spline_at(g, s13, ar, ai);
+      double br[R1] = {}, bi[R1] = {};
+      bw_pairing<double, R, false>(kin, g.res, s12, s13, br, bi, nullptr, nullptr, nullptr, nullptr);
+      bw_pairing<double, R, false>(kin, g.res, s13, s12, br, bi, nullptr, nullptr, nullptr, nullptr);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        ar += g.c[2 * r] * br[r] - g.c[2 * r + 1] * bi[r];
+        ai += g.c[2 * r] * bi[r] + g.c[2 * r + 1] * br[r];
+      }
+      f = ar * ar + ai * ai;
+      if (g.eff) f *= eff_lookup(g.eff, g.nx, g.ny, g.eff_lo, g.eff_hi, s12, s13);
+      if (f > g.fmax) atomicOr(exceeded, 1);
+    }
+    flag = g.mode == 0 ? (in && f > v * g.fmax) : in;
+    o12[i] = s12;
+    o13[i] = s13;
+    of[i] = f;
+    oflag[i] = (unsigned char)flag;
+  }
+  const int cnt = __syncthreads_count(flag);
+  if (threadIdx.x == 0) block_counts[blockIdx.x] = cnt;
+}
+
+__global__ void k_scan(const int* __restrict__ counts, int nb, int* __restrict__ offsets, int* __restrict__ total) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int s = 0;
+    for (int b = 0; b < nb; ++b) {
+      offsets[b] = s;
+      s += counts[b];
+    }
+    *total = s;
+  }
+}
+
+__global__ __launch_bounds__(kGenBlock) void k_scatter(const unsigned char* __restrict__ flag, int count,
+                                                       const int* __restrict__ offsets, const double* __restrict__ a,
+                                                       const double* __restrict__ b, const double* __restrict__ c,
+                                                       double* __restrict__ oa, double* __restrict__ ob,
+                                                       double* __restrict__ oc) {
+  __shared__ int wsum[kGenBlock / 64];
+  const int i = blockIdx.x * kGenBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool fl = i < count && flag[i];
+  const unsigned long long bal = __ballot(fl);
+  const int lp = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wsum[wave] = __popcll(bal);
+  __syncthreads();
+  int woff = 0;
+  for (int w = 0; w < wave; ++w) woff += wsum[w];
+  if (fl) {
+    const int o = offsets[blockIdx.x] + woff + lp;
+    if (oa) oa[o] = a[i];
+    if (ob) ob[o] = b[i];
+    if (oc) oc[o] = c[i];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+
+namespace {
+template <typename Real>
+hipError_t cache_impl(int R, const Segment* s, const void* table, const void* kin, hipStream_t st) {
+  const Kin<Real>& k = *(const Kin<Real>*)kin;
+  const Real* tab = (const Real*)table;
+  const long long want = (s->n + 255) / 256;
+  const int grid = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+  switch (R) {
+    case 0: return hipSuccess;
+    case 1: k_cache<Real, 1><<<grid, 256, 0, st>>>(*s, tab, k); break;
+    case 2: k_cache<Real, 2><<<grid, 256, 0, st>>>(*s, tab, k); break;
+    case 3: k_cache<Real, 3><<<grid, 256, 0, st>>>(*s, tab, k); break;
+    case 4: k_cache<Real, 4><<<grid, 256, 0, st>>>(*s, tab, k); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real, bool OTF>
+hipError_t eval_impl2(int R, const Segment* segs, const int* bs, int nb, int waves, int max_nint, const void* kin,
+                      hipStream_t st) {
+  const Kin<Real>& k = *(const Kin<Real>*)kin;
+  const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
+  const size_t lds = (size_t)waves * (8 * max_nint + nsc) * sizeof(double);
+  const dim3 grid(nb), block(64 * waves);
+  switch (R) {
+    case 0: k_eval<Real, 0, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
+    case 1: k_eval<Real, 1, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
+    case 2: k_eval<Real, 2, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
+    case 3: k_eval<Real, 3, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
+    case 4: k_eval<Real, 4, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t integrals_impl(int R, const Segment* s, const void* w, double* rec, int nb, double* out, hipStream_t st) {
+  const Real* ws = (const Real*)w;
+  switch (R) {
+    case 0: k_integrals<Real, 0><<<nb, 256, 0, st>>>(*s, ws, rec); break;
+    case 1: k_integrals<Real, 1><<<nb, 256, 0, st>>>(*s, ws, rec); break;
+    case 2: k_integrals<Real, 2><<<nb, 256, 0, st>>>(*s, ws, rec); break;
+    case 3: k_integrals<Real, 3><<<nb, 256, 0, st>>>(*s, ws, rec); break;
+    case 4: k_integrals<Real, 4><<<nb, 256, 0, st>>>(*s, ws, rec); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int rs = 2 * (R + 1) * (R + 1);
+  k_sum_records<<<(rs + 63) / 64, 256, 0, st>>>(rec, nb, rs, out);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_cache(bool fp64, int R, const Segment* s, const void* table, const void* kin, hipStream_t st) {
+  return fp64 ? cache_impl<double>(R, s, table, kin, st) : cache_impl<float>(R, s, table, kin, st);
+}
+
+hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const int* bs, int nb, int waves,
+                       int max_nint, const void* kin, hipStream_t st) {
+  if (fp64) return otf ? eval_impl2<double, true>(R, segs, bs, nb, waves, max_nint, kin, st)
+                       : eval_impl2<double, false>(R, segs, bs, nb, waves, max_nint, kin, st);
+  return otf ? eval_impl2<float, true>(R, segs, bs, nb, waves, max_nint, kin, st)
+             : eval_impl2<float, false>(R, segs, bs, nb, waves, max_nint, kin, st);
+}
+
+hipError_t launch_finish(const Job* jobs, int n_jobs, int max_chunks, int, hipStream_t st) {
+  k_finish<<<dim3(max_chunks, n_jobs), 256, 0, st>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_integrals(bool fp64, int R, const Segment* s, const void* w, double* rec, int nb, double* out,
+                            hipStream_t st) {
+  return fp64 ? integrals_impl<double>(R, s, w, rec, nb, out, st) : integrals_impl<float>(R, s, w, rec, nb, out, st);
+}
+
+hipError_t launch_eff_lookup(const double* s12, const double* s13, long long n, const float* tab, int nx, int ny,
+                             double lo, double hi, double* eps, hipStream_t st) {
+  const long long want = (n + 255) / 256;
+  const int grid = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+  k_eff<<<grid, 256, 0, st>>>(s12, s13, n, tab, nx, ny, lo, hi, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_generate_chunk(const GenArgs& g, const void* kin, long long first, int count, double* o12,
+                                 double* o13, double* of, unsigned char* oflag, int* bc, int* exc, hipStream_t st) {
+  const Kin<double>& k = *(const Kin<double>*)kin;
+  const int nb = (count + kGenBlock - 1) / kGenBlock;
+  switch (g.R) {
+    case 0: k_generate<0><<<nb, kGenBlock, 0, st>>>(g, k, first, count, o12, o13, of, oflag, bc, exc); break;
+    case 1: k_generate<1><<<nb, kGenBlock, 0, st>>>(g, k, first, count, o12, o13, of, oflag, bc, exc); break;
+    case 2: k_generate<2><<<nb, kGenBlock, 0, st>>>(g, k, first, count, o12, o13, of, oflag, bc, exc); break;
+    case 3: k_generate<3><<<nb, kGenBlock, 0, st>>>(g, k, first, count, o12, o13, of, oflag, bc, exc); break;
+    case 4: k_generate<4><<<nb, kGenBlock, 0, st>>>(g, k, first, count, o12, o13, of, oflag, bc, exc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const unsigned char* flag, int count, const int* counts, int* offsets, int* total,
+                          const double* a, const double* b, const double* c, double* oa, double* ob, double* oc,
+                          hipStream_t st) {
+  const int nb = (count + kGenBlock - 1) / kGenBlock;
+  k_scan<<<1, 64, 0, st>>>(counts, nb, offsets, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scatter<<<nb, kGenBlock, 0, st>>>(flag, count, offsets, a, b, c, oa, ob, oc);
+  return hipGetLastError();
+}
+
+}  // namespace mipwa

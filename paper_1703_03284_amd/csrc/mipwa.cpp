@@ -1,0 +1,449 @@
+// C ABI of libmipwa: contexts, evaluation, integrals, toy generation.  The fit lives in fit.cpp and
+// the serving loop in serve.cpp.
+#include "mipwa.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace mipwa;
+
+#define HIPCHK(expr, what)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) return ctx->fail(MIPWA_E_HIP, std::string(what) + ": " + \
+                                                             hipGetErrorString(e_)); \
+  } while (0)
+
+int mipwa_ctx::fail(int code, const std::string& msg) {
+  err = msg;
+  return code;
+}
+
+namespace {
+
+int default_blocks(int device) {
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  return 4 * cus;
+}
+
+}  // namespace
+
+// ---- device descriptors and tables -----------------------------------------------------------
+
+int mipwa_ctx::rebuild_launch() {
+  mipwa_ctx* ctx = this;
+  const int total_tiles = ev.n_tiles + nm.n_tiles;
+  int B = std::max(2, std::min(blocks_cfg, std::max(2, total_tiles / (2 * waves_cfg))));
+  nb_d = (int)std::llround((double)B * ev.n_tiles / std::max(total_tiles, 1));
+  nb_d = std::min(std::max(nb_d, 1), B - 1);
+  nb_n = B - nb_d;
+  n_blocks = B;
+  const int nint = mh.N - 1;
+  rs = record_size(nint, mh.R, otf);
+  const int rs_max = record_size(nint, mh.R, true);
+  HIPCHK(d_records.alloc((size_t)B * rs_max * sizeof(double)), "records allocation");
+  std::vector<int> bs(B);
+  for (int b = 0; b < B; ++b) bs[b] = b < nb_d ? 0 : 1;
+  HIPCHK(d_block_seg.alloc(B * sizeof(int)), "block map allocation");
+  HIPCHK(hipMemcpy(d_block_seg.p, bs.data(), B * sizeof(int), hipMemcpyHostToDevice), "block map upload");
+  Segment sg[2];
+  std::memset(sg, 0, sizeof(sg));
+  PointSet* ps[2] = {&ev, &nm};
+  for (int k = 0; k < 2; ++k) {
+    sg[k].tt = ps[k]->tt.p;
+    sg[k].ss = ps[k]->ss.p;
+    sg[k].w = k ? ps[k]->w.p : nullptr;
+    sg[k].cache = ps[k]->cache.p;
+    sg[k].tiles = ps[k]->tiles.as<Tile>();
+    sg[k].table = d_blob.p;
+    sg[k].records = d_records.as<double>() + (size_t)(k ? nb_d : 0) * rs;
+    sg[k].n = ps[k]->n;
+    sg[k].n_tiles = ps[k]->n_tiles;
+    sg[k].kind = k;
+    sg[k].nint = nint;
+    sg[k].rs = rs;
+    sg[k].block0 = k ? nb_d : 0;
+    sg[k].n_blocks = k ? nb_n : nb_d;
+  }
+  std::memcpy(h_segs, sg, sizeof(sg));
+  HIPCHK(d_segs.alloc(sizeof(sg)), "segment allocation");
+  HIPCHK(hipMemcpy(d_segs.p, sg, sizeof(sg), hipMemcpyHostToDevice), "segment upload");
+  Job jb;
+  std::memset(&jb, 0, sizeof(jb));
+  jb.rec_d = sg[0].records;
+  jb.rec_n = sg[1].records;
+  jb.nb_d = nb_d;
+  jb.nb_n = nb_n;
+  jb.fin = d_fin.as<double>();
+  jb.tab64 = d_blob.as<double>() + tab64_off / sizeof(double);
+  jb.out = d_out.as<double>();
+  jb.counter = d_counter.as<unsigned int>();
+  jb.n_ev = (double)ev.n;
+  jb.c_eps = ev.c_eps;
+  jb.N = mh.N;
+  jb.R = mh.R;
+  jb.rs = rs;
+  jb.otf = otf ? 1 : 0;
+  jb.n_chunks = (2 * rs + 63) / 64;
+  HIPCHK(hipMemcpy(d_job.p, &jb, sizeof(jb), hipMemcpyHostToDevice), "job upload");
+  launch_dirty = false;
+  return MIPWA_OK;
+}
+
+int mipwa_ctx::stage_params() {
+  mipwa_ctx* ctx = this;
+  // wait until the previous upload has left the pinned staging buffer
+  HIPCHK(hipEventSynchronize(ev_upload), "staging wait");
+  const int nint = mh.N - 1, R = mh.R;
+  std::vector<double> tab(table_words(nint, R));
+  mh.poly_table(theta.data(), tab.data());
+  for (int r = 0; r < R; ++r) {
+    const double cm = theta[2 * mh.N + 2 * r], ca = theta[2 * mh.N + 2 * r + 1];
+    tab[8 * nint + 2 * r] = cm * std::cos(ca);
+    tab[8 * nint + 2 * r + 1] = cm * std::sin(ca);
+  }
+  mh.res_table(theta.data(), tab.data() + 8 * nint + 2 * R);
+  char* hb = h_blob.as<char>();
+  if (fp64) {
+    std::memcpy(hb, tab.data(), tab.size() * sizeof(double));
+  } else {
+    float* f = reinterpret_cast<float*>(hb);
+    for (size_t i = 0; i < tab.size(); ++i) f[i] = (float)tab[i];
+  }
+  std::memcpy(hb + tab64_off, theta.data(), mh.P * sizeof(double));
+  return MIPWA_OK;
+}
+
+bool mipwa_ctx::shapes_changed() const {
+  if (!cache_valid) return true;
+  for (int p = 2 * mh.N + 2 * mh.R; p < mh.P; ++p)
+    if (theta[p] != cache_shape[p - 2 * mh.N - 2 * mh.R]) return true;
+  return false;
+}
+
+int mipwa_ctx::ensure_cache(hipStream_t st) {
+  mipwa_ctx* ctx = this;
+  if (!shapes_changed()) return MIPWA_OK;
+  PointSet* ps[2] = {&ev, &nm};
+  for (int k = 0; k < 2; ++k) {
+    if (!ps[k]->loaded) continue;
+    HIPCHK(launch_cache(fp64, mh.R, &h_segs[k], d_blob.p, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32, st),
+           "resonance cache kernel");
+  }
+  cache_shape.assign(theta.begin() + 2 * mh.N + 2 * mh.R, theta.end());
+  cache_valid = ev.loaded && nm.loaded;
+  return MIPWA_OK;
+}
+
+int mipwa_ctx::enqueue_eval(hipStream_t st) {
+  mipwa_ctx* ctx = this;
+  if (!ev.loaded || !nm.loaded) return fail(MIPWA_E_STATE, "load events and normalisation points first");
+  if (!have_theta) return fail(MIPWA_E_STATE, "set parameters first");
+  if (launch_dirty) {
+    int rc = rebuild_launch();
+    if (rc) return rc;
+  }
+  int rc = stage_params();
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(ev_t0, st), "event");
+  HIPCHK(hipMemcpyAsync(d_blob.p, h_blob.p, upload_bytes, hipMemcpyHostToDevice, st), "parameter upload");
+  HIPCHK(hipEventRecord(ev_upload, st), "event");
+  if (!otf) {
+    rc = ensure_cache(st);
+    if (rc) return rc;
+  }
+  HIPCHK(hipEventRecord(ev_t1, st), "event");
+  HIPCHK(launch_eval(fp64, mh.R, otf, d_segs.as<Segment>(), d_block_seg.as<int>(), n_blocks, waves_cfg, mh.N - 1,
+                     fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32, st),
+         "likelihood kernel");
+  HIPCHK(hipEventRecord(ev_t2, st), "event");
+  HIPCHK(launch_finish(d_job.as<Job>(), 1, (2 * rs + 63) / 64, mh.N, st), "reduction kernel");
+  HIPCHK(hipEventRecord(ev_t3, st), "event");
+  timing_pending = true;
+  return MIPWA_OK;
+}
+
+// ---- C ABI -----------------------------------------------------------------------------------
+
+extern "C" {
+
+const char* mipwa_strerror(int s) {
+  switch (s) {
+    case MIPWA_OK: return "ok";
+    case MIPWA_E_INVAL: return "invalid argument";
+    case MIPWA_E_NOMEM: return "out of memory or over budget";
+    case MIPWA_E_HIP: return "HIP runtime error";
+    case MIPWA_E_STATE: return "call out of order";
+    case MIPWA_E_DOMAIN: return "non-finite likelihood";
+    case MIPWA_E_NOCONV: return "fit did not converge";
+    case MIPWA_E_CANCELLED: return "cancelled";
+    case MIPWA_E_BUSY: return "no result yet";
+    default: return "unknown status";
+  }
+}
+
+int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx** out) {
+  if (!out) return MIPWA_E_INVAL;
+  *out = nullptr;
+  if (precision != MIPWA_FP64 && precision != MIPWA_MIXED) return MIPWA_E_INVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MIPWA_E_HIP;
+  if (device < 0 || device >= ndev) return MIPWA_E_INVAL;
+  mipwa_ctx* ctx = new (std::nothrow) mipwa_ctx();
+  if (!ctx) return MIPWA_E_NOMEM;
+  ctx->device = device;
+  ctx->fp64 = precision == MIPWA_FP64;
+  std::string err;
+  int rc = ctx->mh.init(model, err);
+  if (rc) {
+    delete ctx;
+    return rc;
+  }
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete ctx;
+    return MIPWA_E_HIP;
+  }
+  for (hipEvent_t* e : {&ctx->ev_upload, &ctx->ev_t0, &ctx->ev_t1, &ctx->ev_t2, &ctx->ev_t3})
+    if (hipEventCreate(e) != hipSuccess) {
+      delete ctx;
+      return MIPWA_E_HIP;
+    }
+  const mipwa::ModelHost& mh = ctx->mh;
+  const size_t real = ctx->fp64 ? 8 : 4;
+  const size_t tbytes = table_words(mh.N - 1, mh.R) * real;
+  ctx->tab64_off = (tbytes + 255) / 256 * 256;
+  ctx->upload_bytes = ctx->tab64_off + mh.P * sizeof(double);
+  const size_t blob = ctx->tab64_off + ((size_t)mh.P + (size_t)mh.N * mh.N + mh.N) * sizeof(double);
+  if (ctx->d_blob.alloc(blob) != hipSuccess || ctx->h_blob.alloc(ctx->upload_bytes) != hipSuccess ||
+      ctx->d_fin.alloc(2 * record_size(mh.N - 1, mh.R, true) * sizeof(double)) != hipSuccess ||
+      ctx->d_counter.alloc(64) != hipSuccess || ctx->d_out.alloc((1 + mh.P) * sizeof(double)) != hipSuccess ||
+      ctx->h_out.alloc((1 + mh.P) * sizeof(double)) != hipSuccess || ctx->d_job.alloc(sizeof(Job)) != hipSuccess) {
+    delete ctx;
+    return MIPWA_E_NOMEM;
+  }
+  // constant part of the FP64 table: K^T and h after theta
+  std::vector<double> cst((size_t)mh.N * mh.N + mh.N - 1);
+  std::copy(mh.KT.begin(), mh.KT.end(), cst.begin());
+  std::copy(mh.h.begin(), mh.h.end(), cst.begin() + (size_t)mh.N * mh.N);
+  if (hipMemcpy(ctx->d_blob.as<char>() + ctx->tab64_off + mh.P * sizeof(double), cst.data(),
+                cst.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(ctx->d_counter.p, 0, 64) != hipSuccess || hipEventRecord(ctx->ev_upload, ctx->stream) != hipSuccess) {
+    delete ctx;
+    return MIPWA_E_HIP;
+  }
+  ctx->fixed.assign(mh.P, 0);
+  for (int p = 2 * mh.N + 2 * mh.R; p < mh.P; ++p) ctx->fixed[p] = 1;
+  ctx->blocks_cfg = default_blocks(device);
+  ctx->waves_cfg = 4;
+  *out = ctx;
+  return MIPWA_OK;
+}
+
+void mipwa_destroy(mipwa_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+const char* mipwa_last_error(const mipwa_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+int mipwa_n_params(const mipwa_ctx* ctx) { return ctx ? ctx->mh.P : MIPWA_E_INVAL; }
+
+int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (blocks < 0 || waves < 0 || waves > 8) return ctx->fail(MIPWA_E_INVAL, "waves per block must be 1..8");
+  ctx->blocks_cfg = blocks ? blocks : default_blocks(ctx->device);
+  ctx->waves_cfg = waves ? waves : 4;
+  ctx->launch_dirty = true;
+  return MIPWA_OK;
+}
+
+int mipwa_set_eff_table(mipwa_ctx* ctx, const float* table, int nx, int ny, double lo, double hi) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!table || nx < 2 || ny < 2 || !(hi > lo)) return ctx->fail(MIPWA_E_INVAL, "efficiency table needs nx, ny >= 2, hi > lo");
+  for (long i = 0; i < (long)nx * ny; ++i)
+    if (!(table[i] > 0) || !std::isfinite(table[i]))
+      return ctx->fail(MIPWA_E_INVAL, "efficiency table values must be positive");
+  (void)hipSetDevice(ctx->device);
+  ctx->eff.tab.assign(table, table + (size_t)nx * ny);
+  ctx->eff.nx = nx;
+  ctx->eff.ny = ny;
+  ctx->eff.lo = lo;
+  ctx->eff.hi = hi;
+  HIPCHK(ctx->eff.d.alloc((size_t)nx * ny * sizeof(float)), "efficiency table allocation");
+  HIPCHK(hipMemcpy(ctx->eff.d.p, table, (size_t)nx * ny * sizeof(float), hipMemcpyHostToDevice), "efficiency table upload");
+  return MIPWA_OK;
+}
+
+int mipwa_load_events(mipwa_ctx* ctx, const double* s12, const double* s13, const double* eff, int64_t n) {
+  if (!ctx) return MIPWA_E_INVAL;
+  (void)hipSetDevice(ctx->device);
+  HIPCHK(hipStreamSynchronize(ctx->stream), "stream sync");
+  int rc = load_points(ctx->mh, ctx->fp64, 0, s12, s13, nullptr, eff, n, ctx->eff, ctx->stream, ctx->ev, ctx->err);
+  ctx->cache_valid = false;
+  ctx->launch_dirty = true;
+  return rc;
+}
+
+int mipwa_load_norm(mipwa_ctx* ctx, const double* s12, const double* s13, const double* w, const double* eff,
+                    int64_t n) {
+  if (!ctx) return MIPWA_E_INVAL;
+  (void)hipSetDevice(ctx->device);
+  HIPCHK(hipStreamSynchronize(ctx->stream), "stream sync");
+  int rc = load_points(ctx->mh, ctx->fp64, 1, s12, s13, w, eff, n, ctx->eff, ctx->stream, ctx->nm, ctx->err);
+  ctx->cache_valid = false;
+  ctx->launch_dirty = true;
+  return rc;
+}
+
+int mipwa_set_fixed(mipwa_ctx* ctx, const unsigned char* fixed, int n) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!fixed || n != ctx->mh.P) return ctx->fail(MIPWA_E_INVAL, "fixed mask must have P entries");
+  ctx->fixed.assign(fixed, fixed + n);
+  bool otf = false;
+  for (int p = 2 * ctx->mh.N + 2 * ctx->mh.R; p < ctx->mh.P; ++p) otf |= fixed[p] == 0;
+  if (otf != ctx->otf) {
+    ctx->otf = otf;
+    ctx->launch_dirty = true;
+  }
+  return MIPWA_OK;
+}
+
+int mipwa_set_params(mipwa_ctx* ctx, const double* theta, int n) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!theta || n != ctx->mh.P) return ctx->fail(MIPWA_E_INVAL, "theta must have P entries");
+  int rc = ctx->mh.check_theta(theta, ctx->err);
+  if (rc) return rc;
+  ctx->theta.assign(theta, theta + n);
+  ctx->have_theta = true;
+  return MIPWA_OK;
+}
+
+int mipwa_eval(mipwa_ctx* ctx, double* nll, double* grad) {
+  if (!ctx) return MIPWA_E_INVAL;
+  (void)hipSetDevice(ctx->device);
+  int rc = ctx->enqueue_eval(ctx->stream);
+  if (rc) return rc;
+  const size_t bytes = (1 + ctx->mh.P) * sizeof(double);
+  HIPCHK(hipMemcpyAsync(ctx->h_out.p, ctx->d_out.p, bytes, hipMemcpyDeviceToHost, ctx->stream), "result copy");
+  HIPCHK(hipStreamSynchronize(ctx->stream), "stream sync");
+  const double* o = ctx->h_out.as<double>();
+  if (nll) *nll = o[0];
+  if (grad) std::memcpy(grad, o + 1, ctx->mh.P * sizeof(double));
+  if (!std::isfinite(o[0])) {
+    if (nll) *nll = INFINITY;
+    return ctx->fail(MIPWA_E_DOMAIN, "-2 ln L is not finite (|A|^2 = 0 at an event?)");
+  }
+  return MIPWA_OK;
+}
+
+int mipwa_eval_async(mipwa_ctx* ctx, void* stream, double* d_out) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!d_out) return ctx->fail(MIPWA_E_INVAL, "d_out is NULL");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ctx->enqueue_eval(st);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(d_out, ctx->d_out.p, (1 + ctx->mh.P) * sizeof(double), hipMemcpyDeviceToDevice, st),
+         "result copy");
+  return MIPWA_OK;
+}
+
+int mipwa_last_timing(const mipwa_ctx* cctx, double* total_ms, double* stream_ms) {
+  mipwa_ctx* ctx = const_cast<mipwa_ctx*>(cctx);
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!ctx->timing_pending) return ctx->fail(MIPWA_E_STATE, "no evaluation timed yet");
+  HIPCHK(hipEventSynchronize(ctx->ev_t3), "event sync");
+  float a = 0, b = 0;
+  HIPCHK(hipEventElapsedTime(&a, ctx->ev_upload, ctx->ev_t3), "event time");
+  HIPCHK(hipEventElapsedTime(&b, ctx->ev_t1, ctx->ev_t2), "event time");
+  if (total_ms) *total_ms = a;
+  if (stream_ms) *stream_ms = b;
+  return MIPWA_OK;
+}
+
+int mipwa_integrals(mipwa_ctx* ctx, int with_eff, double* Ijk) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!Ijk) return ctx->fail(MIPWA_E_INVAL, "Ijk is NULL");
+  if (!ctx->nm.loaded) return ctx->fail(MIPWA_E_STATE, "load normalisation points first");
+  if (!ctx->have_theta) return ctx->fail(MIPWA_E_STATE, "set parameters first");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  if (ctx->launch_dirty && ctx->ev.loaded) {
+    int rc = ctx->rebuild_launch();
+    if (rc) return rc;
+  }
+  int rc = ctx->stage_params();
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(ctx->d_blob.p, ctx->h_blob.p, ctx->upload_bytes, hipMemcpyHostToDevice, st), "upload");
+  HIPCHK(hipEventRecord(ctx->ev_upload, st), "event");
+  // the normalisation segment with its cache valid at the current shapes
+  Segment sg;
+  std::memset(&sg, 0, sizeof(sg));
+  sg.tt = ctx->nm.tt.p;
+  sg.ss = ctx->nm.ss.p;
+  sg.w = ctx->nm.w.p;
+  sg.cache = ctx->nm.cache.p;
+  sg.tiles = ctx->nm.tiles.as<Tile>();
+  sg.table = ctx->d_blob.p;
+  sg.n = ctx->nm.n;
+  sg.n_tiles = ctx->nm.n_tiles;
+  sg.kind = 1;
+  sg.nint = ctx->mh.N - 1;
+  HIPCHK(launch_cache(ctx->fp64, ctx->mh.R, &sg, ctx->d_blob.p,
+                      ctx->fp64 ? (const void*)&ctx->mh.kin64 : (const void*)&ctx->mh.kin32, st),
+         "resonance cache kernel");
+  ctx->cache_valid = false;  // the event cache was not rebuilt for these shapes
+  const int K = ctx->mh.R + 1;
+  const int nb = std::max(1, std::min(1024, (ctx->nm.n_tiles + 3) / 4));
+  DevBuf rec, out;
+  HIPCHK(rec.alloc((size_t)nb * 2 * K * K * sizeof(double)), "integral records");
+  HIPCHK(out.alloc(2 * K * K * sizeof(double)), "integral output");
+  HIPCHK(launch_integrals(ctx->fp64, ctx->mh.R, &sg, with_eff ? ctx->nm.w.p : ctx->nm.wplain.p, rec.as<double>(), nb,
+                          out.as<double>(), st),
+         "integral kernel");
+  HIPCHK(hipStreamSynchronize(st), "stream sync");
+  HIPCHK(hipMemcpy(Ijk, out.p, 2 * K * K * sizeof(double), hipMemcpyDeviceToHost), "integral copy");
+  return MIPWA_OK;
+}
+
+int mipwa_fit_fractions(mipwa_ctx* ctx, double* ff) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!ff) return ctx->fail(MIPWA_E_INVAL, "ff is NULL");
+  const int K = ctx->mh.R + 1, N = ctx->mh.N;
+  std::vector<double> I(2 * K * K);
+  int rc = mipwa_integrals(ctx, 0, I.data());
+  if (rc) return rc;
+  std::vector<double> cr(K), ci(K);
+  cr[0] = 1.0;
+  ci[0] = 0.0;
+  for (int r = 0; r < ctx->mh.R; ++r) {
+    const double m = ctx->theta[2 * N + 2 * r], a = ctx->theta[2 * N + 2 * r + 1];
+    cr[r + 1] = m * std::cos(a);
+    ci[r + 1] = m * std::sin(a);
+  }
+  double tot = 0.0;
+  for (int j = 0; j < K; ++j)
+    for (int k = 0; k < K; ++k) {
+      // Re(c_j conj(c_k) I_jk)
+      const double pr = cr[j] * cr[k] + ci[j] * ci[k], pi = ci[j] * cr[k] - cr[j] * ci[k];
+      const double v = pr * I[2 * (j * K + k)] - pi * I[2 * (j * K + k) + 1];
+      ff[j * K + k] = v;
+      tot += v;
+    }
+  for (int i = 0; i < K * K; ++i) ff[i] /= tot;
+  return MIPWA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+"""Seeded problems shared by the GPU parity tests: the same inputs go to the oracle and to the library."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+import synth
+from oracle import kinematics as K
+from oracle import likelihood as L
+from tests.conftest import oracle_model
+
+
+@dataclass
+class Problem:
+    workload: object
+    model: object           # oracle model
+    knots: np.ndarray
+    theta: np.ndarray
+    events: tuple           # (s12, s13)
+    eff_events: np.ndarray | None
+    norm: tuple             # (s12, s13, w)
+    eff_norm: np.ndarray | None
+    table: np.ndarray | None = None
+
+    @property
+    def log_eps_sum(self):
+        return 0.0 if self.eff_events is None else float(np.sum(np.log(self.eff_events)))
+
+    def oracle_norm(self):
+        s12, s13, w = self.norm
+        return (s12, s13, w if self.eff_norm is None else w * self.eff_norm)
+
+    def oracle(self, theta=None, shapes=False):
+        th = self.theta if theta is None else theta
+        return L.nll_and_grad(self.model, th, self.events, self.oracle_norm(), self.log_eps_sum, shapes=shapes)
+
+    def context(self, precision, table_mode=False):
+        from paper_1703_03284_amd import context_for
+        ctx = context_for(self.workload.decay, self.knots, self.workload.resonances, precision)
+        if table_mode:
+            d = self.workload.decay
+            ctx.set_eff_table(self.table, d.smin, d.smax)
+            ctx.load_events(*self.events)
+            ctx.load_norm(*self.norm)
+        else:
+            ctx.load_events(*self.events, eff=self.eff_events)
+            ctx.load_norm(*self.norm, eff=self.eff_norm)
+        ctx.set_params(self.theta)
+        return ctx
+
+
+def make_problem(workload, n_events, n_norm, seed=0, knots=None, eff="auto", theta=None):
+    kn = workload.knots() if knots is None else np.asarray(knots, dtype=np.float64)
+    m = oracle_model(workload, knots=kn)
+    ev = synth.uniform_phase_space(workload.decay, n_events, 1000 + seed)
+    s12, s13 = synth.uniform_phase_space(workload.decay, n_norm, 2000 + seed)
+    w = np.full(n_norm, K.area(m) / n_norm)
+    mode = workload.efficiency if eff == "auto" else eff
+    e_ev = e_nm = table = None
+    if mode in ("poly", "hist"):
+        pe = synth.PolyEfficiency.seeded(workload.decay, workload.seed("eff"))
+        if mode == "poly":
+            e_ev, e_nm = pe(*ev), pe(s12, s13)
+        else:
+            table = synth.efficiency_histogram(pe)
+            d = workload.decay
+            e_ev = L.hist_lookup(table, d.smin, d.smax, *ev)
+            e_nm = L.hist_lookup(table, d.smin, d.smax, s12, s13)
+    th = workload.start() if theta is None else theta
+    if len(th) != 2 * len(kn) + 4 * workload.n_res:
+        th = synth.perturb_theta(synth.truth_theta(len(kn), workload.resonances, workload.seed("truth")),
+                                 len(kn), workload.n_res, workload.seed("start"))
+    return Problem(workload, m, kn, th, ev, e_ev, (s12, s13, w), e_nm, table)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)

@@ -1,0 +1,216 @@
+"""GPU library vs the FP64 oracle, element by element on the same seeded inputs.
+
+Tolerances: FP64 mode |d(-2 ln L)| <= 1e-10 relative and ||d grad||_inf <= 1e-8 ||grad||_inf;
+mixed mode 1e-6 relative and 1e-4 ||grad||_inf.  Inputs span many tiles, cells with full tiles and
+ragged tails, and points on knots.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fit as OF
+from oracle import generate as OG
+from oracle import kinematics as K
+from oracle import likelihood as L
+from tests.cases import make_problem, rel
+
+pytestmark = pytest.mark.gpu
+
+FP64_NLL, FP64_G = 1e-10, 1e-8
+MIX_NLL, MIX_G = 1e-6, 1e-4
+
+
+def _prec(name):
+    from paper_1703_03284_amd import FP64, MIXED
+    return {"fp64": FP64, "mixed": MIXED}[name]
+
+
+def _check(prob, ctx, tol_nll, tol_g, shapes=False):
+    v_o, g_o = prob.oracle(shapes=shapes)
+    v, g = ctx.eval()
+    assert rel(v, v_o) <= tol_nll, (v, v_o, rel(v, v_o))
+    P = len(g_o)
+    n_ck = 2 * prob.model.n_knots + 2 * prob.model.n_res
+    sel = np.arange(P) if shapes else np.arange(n_ck)
+    err = np.abs(g[sel] - g_o[sel]).max()
+    assert err <= tol_g * np.abs(g_o[sel]).max(), (err, np.abs(g_o[sel]).max())
+    if not shapes:
+        assert np.all(g[n_ck:] == 0.0)
+    return v, g
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("wl,n_ev,n_nm", [(synth.C1, 3000, 20000), (synth.C2, 5000, 30000)])
+def test_nll_and_gradient_match_oracle(prec, wl, n_ev, n_nm):
+    prob = make_problem(wl, n_ev, n_nm, seed=wl.index)
+    ctx = prob.context(_prec(prec))
+    tol = (FP64_NLL, FP64_G) if prec == "fp64" else (MIX_NLL, MIX_G)
+    _check(prob, ctx, *tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_cells_full_tiles_and_ragged_tails(prec):
+    """Five knots: cells hold thousands of points, so tiles are full with one ragged tail per cell."""
+    wl = synth.C2
+    kn = synth.uniform_knots(wl.decay, 5)
+    prob = make_problem(wl, 20000, 50000, seed=7, knots=kn)
+    ctx = prob.context(_prec(prec))
+    tol = (FP64_NLL, FP64_G) if prec == "fp64" else (MIX_NLL, MIX_G)
+    _check(prob, ctx, *tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_histogram_efficiency_lookup(prec):
+    """Efficiency from a 200x200 table, looked up on the device for events and normalisation points."""
+    wl = synth.C3
+    prob = make_problem(wl, 4000, 20000, seed=3)
+    ctx = prob.context(_prec(prec), table_mode=True)
+    tol = (FP64_NLL, FP64_G) if prec == "fp64" else (MIX_NLL, MIX_G)
+    _check(prob, ctx, *tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_mass_and_width_gradient(prec):
+    """Shapes floated: resonance amplitudes and their analytic mass/width derivatives on the fly,
+    against the oracle's five-point differences."""
+    wl = synth.C4
+    prob = make_problem(wl, 3000, 20000, seed=4)
+    ctx = prob.context(_prec(prec))
+    ctx.set_fixed(wl.fixed())
+    tol = (FP64_NLL, 1e-7) if prec == "fp64" else (MIX_NLL, MIX_G)
+    _check(prob, ctx, *tol, shapes=True)
+
+
+def test_mass_width_gradient_vs_finite_differences():
+    """FP64 analytic adjoint vs central differences (h = 1e-6) of the library's own FP64 -2 ln L."""
+    wl = synth.C4
+    prob = make_problem(wl, 2000, 10000, seed=5)
+    ctx = prob.context(_prec("fp64"))
+    ctx.set_fixed(wl.fixed())
+    _, g = ctx.eval(prob.theta)
+    N, R = wl.n_knots, wl.n_res
+    for p in list(range(2 * N + 2 * R, 2 * N + 4 * R)) + [0, 1, 2 * N + 2, 2 * N + 3]:
+        tp, tm = prob.theta.copy(), prob.theta.copy()
+        tp[p] += 1e-6
+        tm[p] -= 1e-6
+        fd = (ctx.eval(tp)[0] - ctx.eval(tm)[0]) / 2e-6
+        assert abs(fd - g[p]) <= 1e-4 * max(1.0, abs(g[p])) + 2e-5 * np.abs(g).max(), (p, fd, g[p])
+
+
+def test_cache_rebuilt_when_shapes_change():
+    wl = synth.C2
+    prob = make_problem(wl, 2000, 10000, seed=8)
+    ctx = prob.context(_prec("fp64"))
+    ctx.eval()
+    th = prob.theta.copy()
+    th[-2] *= 1.05   # a width
+    th[-3] += 0.01   # a mass
+    v, _ = ctx.eval(th)
+    v_o, _ = prob.oracle(theta=th)
+    assert rel(v, v_o) <= FP64_NLL
+
+
+def test_deterministic_bitwise():
+    prob = make_problem(synth.C2, 5000, 30000, seed=9)
+    ctx = prob.context(_prec("mixed"))
+    a = ctx.eval()
+    b = ctx.eval()
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_single_event_single_point_and_knot_positions():
+    wl = synth.C1
+    kn = wl.knots()
+    # points sitting exactly on knots, plus the degenerate one-point sets
+    for ev, nm in [((np.array([0.61]), np.array([1.42])), (np.array([1.1]), np.array([0.95]))),
+                   ((kn[[3, 5, 7]], kn[[9, 6, 8]]), (kn[[2, 4]], kn[[10, 12]]))]:
+        prob = make_problem(wl, 10, 10, seed=1)
+        prob.events = ev
+        prob.norm = (nm[0], nm[1], np.full(len(nm[0]), 0.37))
+        ctx = prob.context(_prec("fp64"))
+        v_o, g_o = prob.oracle()
+        v, g = ctx.eval()
+        assert rel(v, v_o) <= FP64_NLL
+        n_ck = 2 * wl.n_knots + 2 * wl.n_res
+        assert np.abs(g[:n_ck] - g_o[:n_ck]).max() <= FP64_G * np.abs(g_o[:n_ck]).max() + 1e-12
+
+
+def test_errors_are_reported_not_crashed():
+    from paper_1703_03284_amd import MipwaError, context_for
+    wl = synth.C1
+    ctx = context_for(wl.decay, wl.knots(), wl.resonances)
+    with pytest.raises(MipwaError) as e:
+        ctx.eval(wl.truth())
+    assert e.value.status == -4   # E_STATE: nothing loaded
+    with pytest.raises(MipwaError) as e:
+        ctx.load_events(np.array([0.01]), np.array([0.02]))
+    assert e.value.status == -1   # outside the Dalitz region
+    with pytest.raises(MipwaError) as e:
+        ctx.set_params(np.zeros(3))
+    assert e.value.status == -1
+    th = wl.truth()
+    th[-1] = -0.1
+    with pytest.raises(MipwaError):
+        ctx.set_params(th)
+    # |A|^2 = 0 at every event -> -2 ln L = +inf, reported as E_DOMAIN
+    prob = make_problem(wl, 100, 1000, seed=2)
+    c2 = prob.context(_prec("fp64"))
+    z = prob.theta.copy()
+    z[:2 * wl.n_knots + 2 * wl.n_res:2] = 0.0
+    with pytest.raises(MipwaError) as e:
+        c2.eval(z)
+    assert e.value.status == -5
+    assert c2.eval(z, raise_domain=False)[0] == float("inf")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_integrals_and_fit_fractions(prec):
+    prob = make_problem(synth.C2, 100, 40000, seed=11)
+    ctx = prob.context(_prec(prec))
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    for with_eff in (True, False):
+        nm = prob.oracle_norm() if with_eff else prob.norm
+        I_o = L.integrals(prob.model, prob.theta, nm)
+        I = ctx.integrals(with_eff=with_eff)
+        assert np.abs(I - I_o).max() <= tol * np.abs(I_o).max()
+    ff = ctx.fit_fractions()
+    ff_o = L.fit_fractions(prob.model, prob.theta, L.integrals(prob.model, prob.theta, prob.norm))
+    assert np.abs(ff - ff_o).max() <= 10 * tol
+    assert abs(ff.sum() - 1.0) < 1e-12
+
+
+def test_generator_draw_for_draw():
+    wl = synth.C1
+    prob = make_problem(wl, 10, 10, seed=0)
+    th = wl.truth()
+    fmax = 1.5 * OG.density_max(prob.model, th, 77 + 1000, 50_000)
+    s12_o, s13_o, exc_o = OG.accept_reject(prob.model, th, 3000, seed=77, fmax=fmax)
+    ctx = prob.context(_prec("fp64"))
+    s12, s13, exc, ncand = ctx.generate(th, 3000, seed=77, fmax=fmax)
+    assert exc == exc_o
+    assert np.array_equal(s12, s12_o) and np.array_equal(s13, s13_o)
+    assert ctx.density_max(th, 77 + 1000, 50_000) == pytest.approx(fmax / 1.5, rel=1e-12)
+
+
+@pytest.mark.slow
+def test_fit_parity_small_fit():
+    """Same toy, same start: the library's BFGS fit vs the oracle's (scipy BFGS), |d theta| < 0.01 sigma."""
+    wl = synth.C1
+    prob = make_problem(wl, 10, 10, seed=0)
+    truth = wl.truth()
+    s12, s13, _ = OG.toy(prob.model, truth, wl.n_events, seed=wl.seed("events"), n_probe=200_000)
+    n12, n13 = synth.uniform_phase_space(wl.decay, wl.n_norm, wl.seed("norm"))
+    norm = (n12, n13, np.full(len(n12), K.area(prob.model) / len(n12)))
+    ref = OF.fit(prob.model, wl.start(), (s12, s13), norm, wl.fixed(), gtol=1e-6)
+    from paper_1703_03284_amd import context_for
+    ctx = context_for(wl.decay, wl.knots(), wl.resonances)
+    ctx.load_events(s12, s13)
+    ctx.load_norm(n12, n13, norm[2])
+    res = ctx.fit(wl.start(), fixed=wl.fixed(), tol_edm=1e-8)
+    free = np.flatnonzero(wl.fixed() == 0)
+    d = res.theta - ref["theta"]
+    npair = wl.n_knots + wl.n_res
+    d[1:2 * npair:2] = np.angle(np.exp(1j * d[1:2 * npair:2]))
+    pulls = np.abs(d[free]) / ref["sigma"][free]
+    assert pulls.max() < 0.01, pulls.max()
+    assert np.abs(res.sigma[free] / ref["sigma"][free] - 1).max() < 0.01
