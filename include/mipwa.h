@@ -179,9 +179,63 @@ int mipwa_density_max(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t
  * alone.  Nullable outputs. */
 int mipwa_last_timing(const mipwa_ctx* ctx, double* total_ms, double* stream_ms);
 
+/* Accumulate device timings of every synchronous evaluation (on = 1) from HIP events recorded on the
+ * evaluation's stream; resets the statistics.  mipwa_timing_stats returns the number of timed
+ * evaluations and the mean device time of the whole evaluation (upload to finish) and of the
+ * streaming kernel alone, in milliseconds. */
+int mipwa_set_timing(mipwa_ctx* ctx, int on);
+int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_ms, double* mean_stream_ms);
+
 /* Launch shape of the streaming kernel: blocks (0 = default) and waves per block (0 = default, 1..16).
  * Takes effect at the next load.  Errors: E_INVAL. */
 int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves_per_block);
+
+/* ---- toy-fit serving with continuous batching -------------------------------------------------
+ * A server fits many independent toy samples (Sec. 4: fits of toy samples generated from the
+ * Dalitz-plot PDF) against one shared normalisation sample.  Jobs wait until their device footprint
+ * fits the HBM budget, then load (cell sort and resonance cache on their own stream) and run the BFGS
+ * fit of mipwa_fit in a worker thread.  Every evaluation a job needs is batched with the pending
+ * evaluations of all other active jobs into a single launch of the streaming kernel; jobs admitted
+ * while a step runs join the next one.  A job's result does not depend on which other jobs share
+ * its steps (its kernel blocks and reduction order depend only on its own sizes).  Serving jobs keep
+ * masses and widths fixed.  The server is thread-safe. */
+typedef struct mipwa_server mipwa_server;
+typedef struct {
+  double fits_per_s;   /* finished jobs / (last completion - first submission) */
+  double p50_s, p99_s; /* time-to-fit percentiles (submission to completion) */
+  int64_t n_done, n_active, n_queued;
+  int64_t peak_bytes;  /* largest admitted device footprint (events, scratch, normalisation sets) */
+  int64_t steps;       /* batched launches so far */
+  double mean_batch;   /* mean number of jobs per launch */
+} mipwa_serve_stats;
+
+/* Create a server on `device` in `precision`; hbm_budget_bytes = 0 uses 80% of the free memory.
+ * Errors: E_INVAL, E_HIP. */
+int mipwa_server_create(int device, int precision, size_t hbm_budget_bytes, mipwa_server** out);
+/* The shared normalisation sample (host arrays copied; weights as in mipwa_load_norm).  Must be set
+ * before the first submission and cannot be replaced once a job has used it (E_STATE). */
+int mipwa_server_set_norm(mipwa_server* s, const double* s12, const double* s13, const double* w, int64_t n);
+/* Queue one fit: model, n events (host arrays, copied), start theta0 (P doubles), fixed mask (P bytes,
+ * nullable: the first resonance coefficient and every mass and width fixed), options (nullable:
+ * tol_edm 1e-4, max_iter 1000, no Hessian).  *job_id receives the job's id.  Errors: E_INVAL (model,
+ * theta0, a floated mass or width), E_STATE (no normalisation sample), E_NOMEM (the job alone exceeds
+ * the budget). */
+int mipwa_server_submit(mipwa_server* s, const mipwa_model* model, const double* s12, const double* s13, int64_t n,
+                        const double* theta0, const unsigned char* fixed, const mipwa_fit_opts* opts,
+                        int64_t* job_id);
+/* Result of a job: MIPWA_E_BUSY while queued or running, MIPWA_E_CANCELLED, otherwise the fit status
+ * (MIPWA_OK or MIPWA_E_NOCONV) with theta_out (P doubles, nullable), info (nullable) and the
+ * time-to-fit in seconds (nullable) filled in; another negative code if loading or fitting failed. */
+int mipwa_server_poll(mipwa_server* s, int64_t job_id, double* theta_out, mipwa_fit_info* info, double* latency_s);
+/* As mipwa_server_poll, blocking until the job finishes or timeout_s (> 0) elapses. */
+int mipwa_server_wait(mipwa_server* s, int64_t job_id, double timeout_s, double* theta_out, mipwa_fit_info* info,
+                      double* latency_s);
+/* Cancel a queued or running job (it stops at its next evaluation); other jobs are unaffected. */
+int mipwa_server_cancel(mipwa_server* s, int64_t job_id);
+int mipwa_server_stats(mipwa_server* s, mipwa_serve_stats* stats);
+const char* mipwa_server_last_error(const mipwa_server* s);
+/* Cancel every job, join the worker threads and free the device memory. */
+void mipwa_server_destroy(mipwa_server* s);
 
 #ifdef __cplusplus
 }

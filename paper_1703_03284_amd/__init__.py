@@ -13,7 +13,7 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["Context", "MipwaError", "Resonance", "FitResult", "FP64", "MIXED"]
+__all__ = ["Context", "Server", "MipwaError", "Resonance", "FitResult", "FP64", "MIXED", "context_for"]
 
 FP64, MIXED = L.MIPWA_FP64, L.MIPWA_MIXED
 
@@ -156,6 +156,16 @@ class Context:
         self._check(self._lib.mipwa_last_timing(self._h, C.byref(a), C.byref(b)), "last_timing")
         return a.value, b.value
 
+    def set_timing(self, on=True):
+        """Accumulate device timings (HIP events on the evaluation stream) of every synchronous eval."""
+        self._check(self._lib.mipwa_set_timing(self._h, int(bool(on))), "set_timing")
+
+    def timing_stats(self):
+        """(count, mean device ms of the whole evaluation, mean ms of the streaming kernel)."""
+        n, a, b = C.c_longlong(), C.c_double(), C.c_double()
+        self._check(self._lib.mipwa_timing_stats(self._h, C.byref(n), C.byref(a), C.byref(b)), "timing_stats")
+        return n.value, a.value, b.value
+
     def integrals(self, with_eff=True, theta=None):
         if theta is not None:
             self.set_params(theta)
@@ -216,3 +226,85 @@ def context_for(decay, knots, resonances, precision=FP64, device=0) -> Context:
     width, radius attributes."""
     return Context(decay.M, decay.m1, decay.m2, decay.m3, decay.rD, knots,
                    [Resonance(r.spin, r.mass, r.width, r.radius) for r in resonances], precision, device)
+
+
+class Server:
+    """Toy-fit server with continuous batching (include/mipwa.h, mipwa_server_*)."""
+
+    def __init__(self, precision=MIXED, device=0, hbm_budget_bytes=0):
+        self._lib = L.load()
+        h = C.c_void_p()
+        rc = self._lib.mipwa_server_create(int(device), int(precision), int(hbm_budget_bytes), C.byref(h))
+        if rc != 0:
+            raise MipwaError(rc, "mipwa_server_create")
+        self._h = h
+        self._models = {}
+
+    def _check(self, rc, what, ok=(0,)):
+        if rc not in ok:
+            raise MipwaError(rc, f"{what}: {self._lib.mipwa_server_last_error(self._h).decode()}")
+        return rc
+
+    def set_norm(self, s12, s13, w):
+        s12, s13 = _f64(s12), _f64(s13)
+        w = _f64(np.broadcast_to(w, s12.shape))
+        self._check(self._lib.mipwa_server_set_norm(self._h, L.dptr(s12), L.dptr(s13), L.dptr(w), len(s12)), "set_norm")
+
+    def submit(self, decay, knots, resonances, s12, s13, theta0, fixed=None, tol_edm=1e-4, max_iter=1000,
+               hessian=False):
+        mh = _ModelHolder(decay.M, decay.m1, decay.m2, decay.m3, decay.rD, knots,
+                          [Resonance(r.spin, r.mass, r.width, r.radius) for r in resonances])
+        s12, s13, th = _f64(s12), _f64(s13), _f64(theta0)
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+        opts = L.FitOptsC(float(tol_edm), int(max_iter), int(bool(hessian)))
+        jid = C.c_longlong()
+        self._check(self._lib.mipwa_server_submit(
+            self._h, C.byref(mh.c), L.dptr(s12), L.dptr(s13), len(s12), L.dptr(th),
+            None if fx is None else fx.ctypes.data_as(C.POINTER(C.c_ubyte)), C.byref(opts), C.byref(jid)), "submit")
+        self._models[jid.value] = len(th)
+        return jid.value
+
+    def _result(self, fn, jid, *extra):
+        P = self._models[jid]
+        th = np.empty(P)
+        info = L.FitInfoC()
+        lat = C.c_double()
+        rc = fn(self._h, jid, *extra, L.dptr(th), C.byref(info), C.byref(lat))
+        if rc == -8:
+            return None
+        self._check(rc, "result", ok=(0, -6, -7))
+        if rc == -7:
+            return {"status": rc}
+        return {"status": rc, "theta": th, "nll": info.nll, "edm": info.edm, "n_iter": info.n_iter,
+                "n_eval": info.n_eval, "latency_s": lat.value}
+
+    def poll(self, jid):
+        return self._result(self._lib.mipwa_server_poll, jid)
+
+    def wait(self, jid, timeout_s=0.0):
+        return self._result(self._lib.mipwa_server_wait, jid, C.c_double(timeout_s))
+
+    def cancel(self, jid):
+        self._check(self._lib.mipwa_server_cancel(self._h, jid), "cancel")
+
+    def stats(self):
+        st = L.ServeStatsC()
+        self._check(self._lib.mipwa_server_stats(self._h, C.byref(st)), "stats")
+        return {k: getattr(st, k) for k, _ in L.ServeStatsC._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mipwa_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

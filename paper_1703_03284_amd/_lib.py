@@ -62,8 +62,10 @@ SIGNATURES = {
     "mipwa_density_max": (C.c_int, [_P, _D, C.c_int, C.c_ulonglong, _I64, _D]),
     "mipwa_last_timing": (C.c_int, [_P, _D, _D]),
     "mipwa_set_launch": (C.c_int, [_P, C.c_int, C.c_int]),
+    "mipwa_set_timing": (C.c_int, [_P, C.c_int]),
+    "mipwa_timing_stats": (C.c_int, [_P, C.POINTER(_I64), _D, _D]),
     "mipwa_server_create": (C.c_int, [C.c_int, C.c_int, C.c_size_t, C.POINTER(_P)]),
-    "mipwa_server_set_norm": (C.c_int, [_P, C.POINTER(ModelC), _D, _D, _D, _I64]),
+    "mipwa_server_set_norm": (C.c_int, [_P, _D, _D, _D, _I64]),
     "mipwa_server_submit": (C.c_int, [_P, C.POINTER(ModelC), _D, _D, _I64, _D, C.POINTER(C.c_ubyte),
                                       C.POINTER(FitOptsC), C.POINTER(_I64)]),
     "mipwa_server_poll": (C.c_int, [_P, _I64, _D, C.POINTER(FitInfoC), _D]),

@@ -30,20 +30,25 @@ struct mipwa_ctx {
   mipwa::HostBuf h_blob;
   size_t tab64_off = 0, upload_bytes = 0;
 
-  mipwa::DevBuf d_segs, d_block_seg, d_records, d_fin, d_counter, d_out, d_job;
-  mipwa::HostBuf h_out;
+  mipwa::DevBuf d_segs, d_block_seg, d_records, d_grec, d_fin, d_gcount, d_out, d_job;
+  mipwa::HostBuf h_out;          // mapped, coherent: the finish writes the results here
+  double* h_out_dev = nullptr;   // device view of h_out
   mipwa::Segment h_segs[2];
-  int blocks_cfg = 1024, waves_cfg = 4;
+  int blocks_cfg = 512, waves_cfg = 0, waves_eff = 8;
   int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0;
   bool launch_dirty = true;
 
-  hipEvent_t ev_upload = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;
+  hipEvent_t ev_staged = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;
   bool timing_pending = false;
+  bool timing_on = false;
+  long long t_count = 0;
+  double t_total = 0.0, t_stream = 0.0;
+
 
   std::string err;
 
   ~mipwa_ctx() {
-    for (hipEvent_t e : {ev_upload, ev_t0, ev_t1, ev_t2, ev_t3})
+    for (hipEvent_t e : {ev_staged, ev_t0, ev_t1, ev_t2, ev_t3})
       if (e) (void)hipEventDestroy(e);
     if (stream) (void)hipStreamDestroy(stream);
   }
@@ -53,5 +58,7 @@ struct mipwa_ctx {
   int stage_params();
   bool shapes_changed() const;
   int ensure_cache(hipStream_t st);
-  int enqueue_eval(hipStream_t st);
+  int prepare_eval(hipStream_t st);
+  int enqueue_kernels(hipStream_t st, bool to_host, bool timed);
+  int run_sync_eval();
 };

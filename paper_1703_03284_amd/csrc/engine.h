@@ -34,6 +34,11 @@ struct Kin {
   Real rD2;             // D barrier radius squared
 };
 
+// Blocks of one segment are reduced in groups of kGroup consecutive blocks: the last block of a
+// group to finish sums the group's records, the last group of a job sums the group records and runs
+// the FP64 finish.  Completion is detected with atomic counters only (no block waits for another).
+constexpr int kGroup = 32;
+
 // One stream of points (data events or normalisation points of one job) and where its per-block
 // partial records go.  Lives in device memory; read with uniform (scalar) loads.
 struct Segment {
@@ -49,25 +54,28 @@ struct Segment {
   int kind;           // 0 = data, 1 = normalisation
   int nint;           // N - 1 spline intervals
   int rs;             // record size in doubles
-  int block0, n_blocks;
-  int pad0, pad1;
-};
-
-// One likelihood evaluation to finish: its two segments' records and the FP64 host table.
-struct Job {
-  const double* rec_d;  // data segment records
-  const double* rec_n;  // normalisation segment records
-  double* fin;          // 2 * rs scratch: reduced data record, reduced normalisation record
-  const double* tab64;  // theta[P], K^T[N*N], h[N-1]
-  double* out;          // 1 + P: -2 ln L, gradient
-  unsigned int* counter;
-  double n_ev;
-  double c_eps;         // -2 sum ln eff over the events
-  int nb_d, nb_n;
-  int N, R, rs, otf;
-  int n_chunks;
+  int n_blocks;       // blocks assigned to this segment
+  int job;            // index of the segment's job in the job array
+  int g0;             // first reduction group of this segment within its job
   int pad;
 };
+
+// One likelihood evaluation to finish (its data and normalisation segments).
+struct Job {
+  const double* tab64;   // theta[P]
+  const double* consts;  // Thomas c'[N-2], 1/pivot[N-2], h[N-1] of the job's knots
+  double* out;           // 1 + P results: -2 ln L, gradient (device or mapped host memory)
+  double* grec;          // (G_d + G_n) x rs group records
+  double* fin;           // 2 x rs: reduced data record, reduced normalisation record
+  unsigned int* gcount;  // G_d + G_n group counters, zero between evaluations
+  unsigned int* jcount;  // job counter, zero between evaluations
+  double n_ev;
+  double c_eps;          // -2 sum ln eff over the events
+  int G_d, G_n;
+  int N, R, rs, otf;
+};
+
+inline int n_groups(int n_blocks) { return (n_blocks + kGroup - 1) / kGroup; }
 
 // Record layout (doubles): [8 * nint spline-polynomial partials (interval j, power m, re/im)]
 // [sum] [2R: sum g conj(R_r)] [OTF: 2R sum g conj(dR_r/dm), 2R sum g conj(dR_r/dGamma)].
@@ -77,9 +85,13 @@ inline int table_words(int nint, int R) { return 8 * nint + 2 * R + kResWords * 
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
 hipError_t launch_cache(bool fp64, int R, const Segment* h_seg, const void* table, const void* kin,
                         hipStream_t stream);
-hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* d_segs, const int* d_block_seg,
-                       int n_blocks, int waves, int max_nint, const void* kin, hipStream_t stream);
-hipError_t launch_finish(const Job* d_jobs, int n_jobs, int max_chunks, int max_N, hipStream_t stream);
+// e0/e1 (nullable): HIP events recorded by the dispatch at the kernel's start and end
+// d_block_map[b] = (segment, block index within that segment) for every block b of the grid; the
+// kernel also reduces and finishes every job of d_jobs.  e0/e1 (nullable): HIP events recorded by the
+// dispatch at the kernel's start and end.
+hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* d_segs, const int2* d_block_map,
+                       const Job* d_jobs, int n_blocks, int waves, int max_nint, const void* kin,
+                       hipStream_t stream, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_integrals(bool fp64, int R, const Segment* h_seg, const void* w_override,
                             double* d_records, int n_blocks, double* d_out, hipStream_t stream);
 hipError_t launch_eff_lookup(const double* d_s12, const double* d_s13, long long n, const float* d_table,

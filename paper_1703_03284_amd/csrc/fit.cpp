@@ -14,12 +14,14 @@
 #include <vector>
 
 #include "ctx.h"
+#include "minimizer.h"
 #include "mipwa.h"
 
+namespace mipwa {
 namespace {
 
 struct Objective {
-  mipwa_ctx* ctx;
+  const FullEval* fg;
   std::vector<int> free;
   std::vector<double> full;
   std::vector<double> gfull;
@@ -28,17 +30,7 @@ struct Objective {
   int operator()(const std::vector<double>& x, double& f, std::vector<double>& g) {
     for (size_t i = 0; i < free.size(); ++i) full[free[i]] = x[i];
     ++n_eval;
-    int rc = mipwa_set_params(ctx, full.data(), (int)full.size());
-    if (rc == MIPWA_E_INVAL) {
-      f = INFINITY;
-      return MIPWA_OK;
-    }
-    if (rc) return rc;
-    rc = mipwa_eval(ctx, &f, gfull.data());
-    if (rc == MIPWA_E_DOMAIN) {
-      f = INFINITY;
-      return MIPWA_OK;
-    }
+    int rc = (*fg)(full.data(), f, gfull.data());
     if (rc) return rc;
     g.resize(free.size());
     for (size_t i = 0; i < free.size(); ++i) g[i] = gfull[free[i]];
@@ -199,27 +191,25 @@ bool cholesky_inverse(std::vector<double> A, size_t n, std::vector<double>& inv)
 
 }  // namespace
 
-extern "C" int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* theta_inout, double* cov_out,
-                         mipwa_fit_info* info) {
-  if (!ctx) return MIPWA_E_INVAL;
-  if (!theta_inout) return ctx->fail(MIPWA_E_INVAL, "theta is NULL");
-  const int P = ctx->mh.P, N = ctx->mh.N, R = ctx->mh.R;
-  const double tol = opts && opts->tol_edm > 0 ? opts->tol_edm : 1e-6;
-  const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 1000;
-  const bool want_hess = opts ? opts->hessian != 0 : true;
-  Objective obj{ctx, {}, std::vector<double>(theta_inout, theta_inout + P), std::vector<double>(P), 0};
+int bfgs_fit(const FullEval& fg, int P, int N, int R, const std::vector<unsigned char>& fixed, const double* theta0,
+             double tol, int max_iter, bool want_hess, double eps_rel, FitOut& out) {
+  Objective obj{&fg, {}, std::vector<double>(theta0, theta0 + P), std::vector<double>(P), 0};
   for (int p = 0; p < P; ++p)
-    if (!ctx->fixed[p]) obj.free.push_back(p);
+    if (!fixed[p]) obj.free.push_back(p);
   const size_t n = obj.free.size();
-  if (n == 0) return ctx->fail(MIPWA_E_INVAL, "every parameter is fixed");
-  std::vector<double> x(n), g, xn, gn;
-  for (size_t i = 0; i < n; ++i) x[i] = theta_inout[obj.free[i]];
+  if (n == 0) {
+    out.err = "every parameter is fixed";
+    return MIPWA_E_INVAL;
+  }
+  std::vector<double> x(n), g;
+  for (size_t i = 0; i < n; ++i) x[i] = theta0[obj.free[i]];
   double f = 0.0;
   int rc = obj(x, f, g);
   if (rc) return rc;
-  if (!std::isfinite(f)) return ctx->fail(MIPWA_E_DOMAIN, "-2 ln L is not finite at the start point");
-  // FP32 streams leave ~1e-11 relative noise in f; allow it in the sufficient-decrease test
-  const double eps_rel = ctx->fp64 ? 1e-13 : 1e-10;
+  if (!std::isfinite(f)) {
+    out.err = "-2 ln L is not finite at the start point";
+    return MIPWA_E_DOMAIN;
+  }
   std::vector<double> B(n * n, 0.0);
   const double gmax = std::max(1e-300, std::fabs(*std::max_element(g.begin(), g.end(), [](double a, double b) {
     return std::fabs(a) < std::fabs(b);
@@ -271,7 +261,7 @@ extern "C" int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* the
       std::vector<double> By;
       matvec(B, y, By);
       const double yBy = dot(y, By);
-      // B + rho^2 (y^T B y) s s^T + rho s s^T - rho (B y s^T + s y^T B)
+      // B + (rho^2 y^T B y + rho) s s^T - rho (B y s^T + s y^T B)
       for (size_t i = 0; i < n; ++i)
         for (size_t j = 0; j < n; ++j)
           B[i * n + j] += (rho * rho * yBy + rho) * s[i] * s[j] - rho * (By[i] * s[j] + s[i] * By[j]);
@@ -311,35 +301,76 @@ extern "C" int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* the
       edm = 0.5 * dot(g, Bg);
     }
   }
-  // restore the evaluation at the minimum (the Hessian loop moved the context's parameters)
-  std::vector<double> gfinal;
-  rc = obj(x, f, gfinal);
-  if (rc) return rc;
-  for (size_t i = 0; i < n; ++i) theta_inout[obj.free[i]] = x[i];
-  // fold (magnitude, phase) pairs: magnitude >= 0, phase in (-pi, pi]
+  out.theta.assign(theta0, theta0 + P);
+  for (size_t i = 0; i < n; ++i) out.theta[obj.free[i]] = x[i];
+  out.cov.assign((size_t)P * P, 0.0);
+  for (size_t i = 0; i < n; ++i)
+    for (size_t j = 0; j < n; ++j) out.cov[(size_t)obj.free[i] * P + obj.free[j]] = V[i * n + j];
+  // fold (magnitude, phase) pairs: magnitude >= 0, phase in (-pi, pi]; a sign flip of a magnitude flips
+  // its covariance row and column
   for (int k = 0; k < N + R; ++k) {
-    double a = theta_inout[2 * k], p = theta_inout[2 * k + 1];
+    double a = out.theta[2 * k], p = out.theta[2 * k + 1];
     if (a < 0) {
       a = -a;
       p += M_PI;
+      for (int q = 0; q < P; ++q) {
+        out.cov[(size_t)(2 * k) * P + q] = -out.cov[(size_t)(2 * k) * P + q];
+        out.cov[(size_t)q * P + 2 * k] = -out.cov[(size_t)q * P + 2 * k];
+      }
     }
     p = M_PI - std::fmod(std::fmod(M_PI - p, 2.0 * M_PI) + 2.0 * M_PI, 2.0 * M_PI);
-    theta_inout[2 * k] = a;
-    theta_inout[2 * k + 1] = p;
+    out.theta[2 * k] = a;
+    out.theta[2 * k + 1] = p;
   }
+  out.nll = f;
+  out.edm = edm;
+  out.n_iter = iter;
+  out.n_eval = obj.n_eval;
+  out.status = status;
+  return MIPWA_OK;
+}
+
+}  // namespace mipwa
+
+extern "C" int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* theta_inout, double* cov_out,
+                         mipwa_fit_info* info) {
+  using namespace mipwa;
+  if (!ctx) return MIPWA_E_INVAL;
+  if (!theta_inout) return ctx->fail(MIPWA_E_INVAL, "theta is NULL");
+  const int P = ctx->mh.P;
+  const double tol = opts && opts->tol_edm > 0 ? opts->tol_edm : 1e-6;
+  const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 1000;
+  const bool want_hess = opts ? opts->hessian != 0 : true;
+  FullEval fg = [ctx, P](const double* th, double& f, double* g) -> int {
+    int rc = mipwa_set_params(ctx, th, P);
+    if (rc == MIPWA_E_INVAL) {
+      f = INFINITY;
+      return MIPWA_OK;
+    }
+    if (rc) return rc;
+    rc = mipwa_eval(ctx, &f, g);
+    if (rc == MIPWA_E_DOMAIN) {
+      f = INFINITY;
+      return MIPWA_OK;
+    }
+    return rc;
+  };
+  // FP32 streams leave ~1e-11 relative noise in f; allow it in the sufficient-decrease test
+  const double eps_rel = ctx->fp64 ? 1e-13 : 1e-10;
+  FitOut out;
+  int rc = bfgs_fit(fg, P, ctx->mh.N, ctx->mh.R, ctx->fixed, theta_inout, tol, max_iter, want_hess, eps_rel, out);
+  if (rc) return ctx->fail(rc, out.err.empty() ? std::string(ctx->err) : out.err);
+  std::copy(out.theta.begin(), out.theta.end(), theta_inout);
   (void)mipwa_set_params(ctx, theta_inout, P);
-  if (cov_out) {
-    std::memset(cov_out, 0, sizeof(double) * P * P);
-    for (size_t i = 0; i < n; ++i)
-      for (size_t j = 0; j < n; ++j) cov_out[(size_t)obj.free[i] * P + obj.free[j]] = V[i * n + j];
-  }
+  if (cov_out) std::copy(out.cov.begin(), out.cov.end(), cov_out);
   if (info) {
-    info->nll = f;
-    info->edm = edm;
-    info->n_iter = iter;
-    info->n_eval = obj.n_eval;
-    info->status = status;
+    info->nll = out.nll;
+    info->edm = out.edm;
+    info->n_iter = out.n_iter;
+    info->n_eval = out.n_eval;
+    info->status = out.status;
   }
-  if (status != MIPWA_OK) return ctx->fail(MIPWA_E_NOCONV, "EDM above tolerance after max_iter iterations or a failed line search");
+  if (out.status != MIPWA_OK)
+    return ctx->fail(MIPWA_E_NOCONV, "EDM above tolerance after max_iter iterations or a failed line search");
   return MIPWA_OK;
 }

@@ -117,15 +117,6 @@ int ModelHost::init(const mipwa_model* m, std::string& err) {
     th_d[i] = den;
     th_c[i] = c / den;
   }
-  // K = dM/dz, column by column
-  KT.assign((size_t)N * N, 0.0);
-  std::vector<double> zr(N), zi(N, 0.0), Mr(N), Mi(N);
-  for (int k = 0; k < N; ++k) {
-    std::fill(zr.begin(), zr.end(), 0.0);
-    zr[k] = 1.0;
-    second_derivs(zr.data(), zi.data(), Mr.data(), Mi.data());
-    for (int i = 0; i < N; ++i) KT[(size_t)k * N + i] = Mr[i];
-  }
   fill_kin(kin64, M, m1, m2, m3, rD);
   fill_kin(kin32, M, m1, m2, m3, rD);
   return MIPWA_OK;

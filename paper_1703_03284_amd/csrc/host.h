@@ -62,10 +62,11 @@ struct HostBuf {
     p = nullptr;
     bytes = 0;
   }
-  hipError_t alloc(size_t n) {
+  hipError_t alloc(size_t n, bool mapped_coherent = false) {
     if (n <= bytes && p) return hipSuccess;
     release();
-    hipError_t e = hipHostMalloc(&p, n ? n : 16, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&p, n ? n : 16,
+                                 mapped_coherent ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault);
     if (e == hipSuccess) bytes = n;
     else p = nullptr;
     return e;
@@ -80,7 +81,6 @@ struct ModelHost {
   std::vector<double> knots, h;  // N knots, N-1 interval lengths
   std::vector<mipwa_res> res;
   int N = 0, R = 0, P = 0;
-  std::vector<double> KT;        // N x N, KT[k*N+i] = dM_i/dz_k (natural spline)
   std::vector<double> th_c;      // Thomas factors (interior unknowns)
   std::vector<double> th_d;
   Kin<double> kin64{};

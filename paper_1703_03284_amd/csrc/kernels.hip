@@ -14,6 +14,7 @@
 // in registers while the cell does not change, and folds them into a wave-private LDS histogram of
 // spline intervals when it does.  Blocks write fixed-size FP64 records; a second kernel reduces them
 // in a fixed order (bitwise reproducible) and runs the FP64 finish.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "engine.h"
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void k_cache(Segment sg, const Real* __restric
 
 template <typename Real, int R, bool OTF, int KIND>
 __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& kin, double* bins,
-                                            double* scal, int wave, int lane, int waves) {
+                                            double* scal, int wave, int lane, int waves, int local_block) {
   using O = Ops<Real>;
   using V2 = typename O::V2;
   constexpr int R1 = R > 0 ? R : 1;
@@ -162,7 +163,7 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   const long long n = sg.n;
 
   const long long nw = (long long)sg.n_blocks * waves;
-  const long long gw = (long long)(blockIdx.x - sg.block0) * waves + wave;
+  const long long gw = (long long)local_block * waves + wave;
   const int t0 = (int)(sg.n_tiles * gw / nw);
   const int t1 = (int)(sg.n_tiles * (gw + 1) / nw);
 
@@ -174,6 +175,16 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
 #pragma unroll
   for (int r = 0; r < 2 * R1; ++r) agc[r] = ahm[r] = ahg[r] = 0.0;
 
+  // FP32 streams: per-tile partial sums in FP32, folded into the FP64 accumulators once per tile.
+  // FP64 streams: the "tile" arrays are the accumulators themselves (never folded per tile).
+  constexpr bool kTilePartial = sizeof(Real) < sizeof(double);
+  Real tq12[8], tq13[8], tgc[2 * R1], thm[2 * R1], thg[2 * R1];
+  Real tacc = Real(0);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) tq12[m] = tq13[m] = Real(0);
+#pragma unroll
+  for (int r = 0; r < 2 * R1; ++r) tgc[r] = thm[r] = thg[r] = Real(0);
+
   int cj12 = -1, cj13 = -1;
   Real p12[8], p13[8];
 #pragma unroll
@@ -182,8 +193,14 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   auto flush = [&]() {
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const double a = wave_sum(q12[m]);
-      const double b = wave_sum(q13[m]);
+      double u = q12[m], v = q13[m];
+      if constexpr (!kTilePartial) {
+        u += (double)tq12[m];
+        v += (double)tq13[m];
+        tq12[m] = tq13[m] = Real(0);
+      }
+      const double a = wave_sum(u);
+      const double b = wave_sum(v);
       q12[m] = 0.0;
       q13[m] = 0.0;
       if (lane == 0) {
@@ -257,55 +274,83 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
           ai += cre[r] * ri[r] + cim[r] * rr[r];
         }
         const Real a2 = ar * ar + ai * ai;
-        Real sr, si;
+        Real gr, gi;
         if constexpr (KIND == 0) {
           const Real l = O::log(a2);
-          acc += valid[k] ? (double)l : 0.0;
-          const Real s = valid[k] ? Real(-4) * O::rcp(a2) : Real(0);
-          sr = s * ar;
-          si = s * ai;
+          tacc += valid[k] ? l : Real(0);
+          const Real sc = valid[k] ? Real(-4) * O::rcp(a2) : Real(0);
+          gr = sc * ar;
+          gi = sc * ai;
         } else {
           const Real w = valid[k] ? wv[k] : Real(0);
-          acc += (double)w * (double)a2;
-          sr = Real(4) * w * ar;
-          si = Real(4) * w * ai;
-        }
-        const double g_r = sr, g_i = si;
-        {
-          const double x = x12, x2 = x * x, x3 = x2 * x;
-          q12[0] += g_r;
-          q12[1] += g_i;
-          q12[2] += g_r * x;
-          q12[3] += g_i * x;
-          q12[4] += g_r * x2;
-          q12[5] += g_i * x2;
-          q12[6] += g_r * x3;
-          q12[7] += g_i * x3;
+          tacc += w * a2;
+          gr = Real(4) * w * ar;
+          gi = Real(4) * w * ai;
         }
         {
-          const double x = x13, x2 = x * x, x3 = x2 * x;
-          q13[0] += g_r;
-          q13[1] += g_i;
-          q13[2] += g_r * x;
-          q13[3] += g_i * x;
-          q13[4] += g_r * x2;
-          q13[5] += g_i * x2;
-          q13[6] += g_r * x3;
-          q13[7] += g_i * x3;
+          const Real x = x12, x2 = x * x, x3 = x2 * x;
+          tq12[0] += gr;
+          tq12[1] += gi;
+          tq12[2] += gr * x;
+          tq12[3] += gi * x;
+          tq12[4] += gr * x2;
+          tq12[5] += gi * x2;
+          tq12[6] += gr * x3;
+          tq12[7] += gi * x3;
+        }
+        {
+          const Real x = x13, x2 = x * x, x3 = x2 * x;
+          tq13[0] += gr;
+          tq13[1] += gi;
+          tq13[2] += gr * x;
+          tq13[3] += gi * x;
+          tq13[4] += gr * x2;
+          tq13[5] += gi * x2;
+          tq13[6] += gr * x3;
+          tq13[7] += gi * x3;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double Rr = rr[r], Ri = ri[r];
-          agc[2 * r] += g_r * Rr + g_i * Ri;
-          agc[2 * r + 1] += g_i * Rr - g_r * Ri;
+          tgc[2 * r] += gr * rr[r] + gi * ri[r];
+          tgc[2 * r + 1] += gi * rr[r] - gr * ri[r];
           if constexpr (OTF) {
-            const double Mr = dmr[r], Mi = dmi[r], Gr = dgr[r], Gi = dgi[r];
-            ahm[2 * r] += g_r * Mr + g_i * Mi;
-            ahm[2 * r + 1] += g_i * Mr - g_r * Mi;
-            ahg[2 * r] += g_r * Gr + g_i * Gi;
-            ahg[2 * r + 1] += g_i * Gr - g_r * Gi;
+            thm[2 * r] += gr * dmr[r] + gi * dmi[r];
+            thm[2 * r + 1] += gi * dmr[r] - gr * dmi[r];
+            thg[2 * r] += gr * dgr[r] + gi * dgi[r];
+            thg[2 * r + 1] += gi * dgr[r] - gr * dgi[r];
           }
         }
+      }
+    }
+    if constexpr (kTilePartial) {
+      acc += (double)tacc;
+      tacc = Real(0);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        q12[m] += (double)tq12[m];
+        q13[m] += (double)tq13[m];
+        tq12[m] = tq13[m] = Real(0);
+      }
+#pragma unroll
+      for (int r = 0; r < 2 * R; ++r) {
+        agc[r] += (double)tgc[r];
+        tgc[r] = Real(0);
+        if constexpr (OTF) {
+          ahm[r] += (double)thm[r];
+          ahg[r] += (double)thg[r];
+          thm[r] = thg[r] = Real(0);
+        }
+      }
+    }
+  }
+  if constexpr (!kTilePartial) {
+    acc += (double)tacc;
+#pragma unroll
+    for (int r = 0; r < 2 * R; ++r) {
+      agc[r] += (double)tgc[r];
+      if constexpr (OTF) {
+        ahm[r] += (double)thm[r];
+        ahg[r] += (double)thg[r];
       }
     }
   }
@@ -332,55 +377,25 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   }
 }
 
-template <typename Real, int R, bool OTF>
-__global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, const int* __restrict__ block_seg,
-                                              Kin<Real> kin, int max_nint) {
-  extern __shared__ double lds[];
-  const int waves = blockDim.x >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const Segment sg = segs[block_seg[blockIdx.x]];
-  const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
-  const int stride = 8 * max_nint;
-  double* bins = lds;
-  double* scal = lds + waves * stride;
-  for (int i = threadIdx.x; i < waves * stride + waves * nsc; i += blockDim.x) lds[i] = 0.0;
-  __syncthreads();
-  if (sg.kind == 0)
-    run_segment<Real, R, OTF, 0>(sg, kin, bins + wave * stride, scal, wave, lane, waves);
-  else
-    run_segment<Real, R, OTF, 1>(sg, kin, bins + wave * stride, scal, wave, lane, waves);
-  __syncthreads();
-  double* rec = sg.records + (long long)(blockIdx.x - sg.block0) * sg.rs;
-  const int nb = 8 * sg.nint;
-  for (int f = threadIdx.x; f < nb + nsc; f += blockDim.x) {
-    double s = 0.0;
-    if (f < nb) {
-      for (int w = 0; w < waves; ++w) s += bins[w * stride + f];
-    } else {
-      for (int w = 0; w < waves; ++w) s += scal[w * nsc + (f - nb)];
-    }
-    rec[f] = s;
-  }
-}
-
 // ---------------------------------------------------------------------------------------------
-// K3: fixed-order reduction of the block records, then the FP64 finish (last block per job):
+// FP64 finish of one job, run by the block that completes the job's last reduction group:
 //   -2 ln L = -2 S_data + C_eps + 2 n ln I,  scale = n / I,
 //   spline-polynomial partials -> knot values z and second derivatives M -> z through M = K z,
 //   then the chain rule to (a_k, phi_k), (|c_r|, arg c_r), (m_r, Gamma_r).
 
 __device__ void finish_job(const Job& jb) {
-  const int N = jb.N, nint = N - 1, R = jb.R, P = 2 * N + 4 * R;
+  const int N = jb.N, nint = N - 1, R = jb.R;
   const double* fd = jb.fin;
   const double* fn = jb.fin + jb.rs;
   const int s0 = 8 * nint;
   const double I = fn[s0];
   const double scale = jb.n_ev / I;
   const double* th = jb.tab64;
-  const double* KT = th + P;
-  const double* h = KT + N * N;
-  __shared__ double gy[2 * kMaxKnots], gm[2 * kMaxKnots];
+  const double* thc = jb.consts;         // Thomas factors c'_i of the interior system
+  const double* thinv = thc + (N - 2);   // 1 / pivot_i
+  const double* h = thinv + (N - 2);
+  __shared__ double gy[2 * kMaxKnots], gm[2 * kMaxKnots], u[2 * kMaxKnots];
+  // spline-polynomial partials of interval j -> partials of z_j, z_{j+1}, M_j, M_{j+1}
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
     double yr = 0, yi = 0, mr = 0, mi = 0;
     if (k < nint) {
@@ -414,13 +429,41 @@ __device__ void finish_job(const Job& jb) {
     gm[2 * k + 1] = mi;
   }
   __syncthreads();
+  // M = T^-1 D z on the interior knots, T symmetric tridiagonal: the z-partials through M are
+  // D^T T^-1 g_M.  One Thomas solve per component (re on wave 0, im on wave 1, or both on thread 0
+  // of a one-wave block).
+  for (int comp = (threadIdx.x >> 6); comp < 2 && (threadIdx.x & 63) == 0;
+       comp += (blockDim.x >= 128 ? 2 : 1)) {
+    const int n = N - 2;
+    double prev = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double a = i > 0 ? h[i] : 0.0;
+      prev = (gm[2 * (i + 1) + comp] - a * prev) * thinv[i];
+      u[2 * (i + 1) + comp] = prev;
+    }
+    for (int i = n - 2; i >= 0; --i) u[2 * (i + 1) + comp] -= thc[i] * u[2 * (i + 2) + comp];
+    u[comp] = 0.0;
+    u[2 * (N - 1) + comp] = 0.0;
+  }
+  __syncthreads();
   double* out = jb.out;
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
     double yr = gy[2 * k], yi = gy[2 * k + 1];
-    for (int i = 0; i < N; ++i) {
-      const double kt = KT[k * N + i];
-      yr += kt * gm[2 * i];
-      yi += kt * gm[2 * i + 1];
+    // D[k', k] for interior rows k' in {k-1, k, k+1}
+    if (k + 1 <= N - 2) {
+      const double d = 6.0 / h[k];
+      yr += d * u[2 * (k + 1)];
+      yi += d * u[2 * (k + 1) + 1];
+    }
+    if (k >= 1 && k <= N - 2) {
+      const double d = -6.0 / h[k] - 6.0 / h[k - 1];
+      yr += d * u[2 * k];
+      yi += d * u[2 * k + 1];
+    }
+    if (k - 1 >= 1) {
+      const double d = 6.0 / h[k - 1];
+      yr += d * u[2 * (k - 1)];
+      yi += d * u[2 * (k - 1) + 1];
     }
     const double a = th[2 * k], ph = th[2 * k + 1];
     double sn, cs;
@@ -449,38 +492,89 @@ __device__ void finish_job(const Job& jb) {
     out[2 + 2 * N + 2 * R + 2 * r] = dg;
   }
   if (threadIdx.x == 0) out[0] = -2.0 * fd[s0] + jb.c_eps + 2.0 * jb.n_ev * log(I);
+  __threadfence_system();
 }
 
-__global__ __launch_bounds__(256) void k_finish(const Job* __restrict__ jobs) {
-  const Job jb = jobs[blockIdx.y];
-  if ((int)blockIdx.x >= jb.n_chunks) return;
-  __shared__ double part[4][64];
-  __shared__ int is_last;
-  const int lane = threadIdx.x & 63, prt = threadIdx.x >> 6;
-  const int f = blockIdx.x * 64 + lane;
-  double acc = 0.0;
-  if (f < 2 * jb.rs) {
-    const bool isn = f >= jb.rs;
-    const int ff = isn ? f - jb.rs : f;
-    const double* rec = isn ? jb.rec_n : jb.rec_d;
-    const int nb = isn ? jb.nb_n : jb.nb_d;
-    for (int b = prt; b < nb; b += 4) acc += rec[(long long)b * jb.rs + ff];
-  }
-  part[prt][lane] = acc;
+template <typename Real, int R, bool OTF>
+__global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, const int2* __restrict__ block_map,
+                                              const Job* __restrict__ jobs, Kin<Real> kin, int max_nint) {
+  extern __shared__ double lds[];
+  __shared__ int s_last;
+  const int waves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int2 bm = block_map[blockIdx.x];  // (segment, block index within the segment)
+  const Segment sg = segs[bm.x];
+  const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
+  const int stride = 8 * max_nint;
+  double* bins = lds;
+  double* scal = lds + waves * stride;
+  for (int i = threadIdx.x; i < waves * stride + waves * nsc; i += blockDim.x) lds[i] = 0.0;
   __syncthreads();
-  if (prt == 0 && f < 2 * jb.rs)
-    jb.fin[f] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+  if (sg.kind == 0)
+    run_segment<Real, R, OTF, 0>(sg, kin, bins + wave * stride, scal, wave, lane, waves, bm.y);
+  else
+    run_segment<Real, R, OTF, 1>(sg, kin, bins + wave * stride, scal, wave, lane, waves, bm.y);
+  __syncthreads();
+  const int rs = sg.rs;
+  double* rec = sg.records + (long long)bm.y * rs;
+  const int nb = 8 * sg.nint;
+  for (int f = threadIdx.x; f < nb + nsc; f += blockDim.x) {
+    double s = 0.0;
+    if (f < nb) {
+      for (int w = 0; w < waves; ++w) s += bins[w * stride + f];
+    } else {
+      for (int w = 0; w < waves; ++w) s += scal[w * nsc + (f - nb)];
+    }
+    rec[f] = s;
+  }
+
+  // reduction tail: last block of the group, then last group of the job
+  const Job* jp = jobs + sg.job;
+  const int g = bm.y / kGroup;
+  const int gsz = min(kGroup, sg.n_blocks - g * kGroup);
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(jb.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = prev == (unsigned)(jb.n_chunks - 1);
+    const unsigned prev =
+        __hip_atomic_fetch_add(jp->gcount + sg.g0 + g, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev == (unsigned)(gsz - 1);
   }
   __syncthreads();
-  if (!is_last) return;
+  if (!s_last) return;
   __threadfence();
+  {
+    const double* rb = sg.records + (long long)g * kGroup * rs;
+    double* go = jp->grec + (long long)(sg.g0 + g) * rs;
+    for (int f = threadIdx.x; f < rs; f += blockDim.x) {
+      double s = 0.0;
+#pragma unroll 8
+      for (int b = 0; b < gsz; ++b) s += rb[(long long)b * rs + f];
+      go[f] = s;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(jp->gcount + sg.g0 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned prev = __hip_atomic_fetch_add(jp->jcount, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev == (unsigned)(jp->G_d + jp->G_n - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const Job jb = *jp;
+  for (int f = threadIdx.x; f < rs; f += blockDim.x) {
+    double d = 0.0, q = 0.0;
+    for (int k = 0; k < jb.G_d; ++k) d += jb.grec[(long long)k * rs + f];
+    for (int k = 0; k < jb.G_n; ++k) q += jb.grec[(long long)(jb.G_d + k) * rs + f];
+    jb.fin[f] = d;
+    jb.fin[rs + f] = q;
+  }
+  __threadfence();
+  __syncthreads();
   finish_job(jb);
-  if (threadIdx.x == 0) __hip_atomic_store(jb.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(jp->jcount, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -739,21 +833,24 @@ hipError_t cache_impl(int R, const Segment* s, const void* table, const void* ki
 }
 
 template <typename Real, bool OTF>
-hipError_t eval_impl2(int R, const Segment* segs, const int* bs, int nb, int waves, int max_nint, const void* kin,
-                      hipStream_t st) {
-  const Kin<Real>& k = *(const Kin<Real>*)kin;
+hipError_t eval_impl2(int R, const Segment* segs, const int2* bs, const Job* jobs, int nb, int waves, int max_nint,
+                      const void* kin, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  Kin<Real> k = *(const Kin<Real>*)kin;
   const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
   const size_t lds = (size_t)waves * (8 * max_nint + nsc) * sizeof(double);
   const dim3 grid(nb), block(64 * waves);
+  const void* fn = nullptr;
   switch (R) {
-    case 0: k_eval<Real, 0, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
-    case 1: k_eval<Real, 1, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
-    case 2: k_eval<Real, 2, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
-    case 3: k_eval<Real, 3, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
-    case 4: k_eval<Real, 4, OTF><<<grid, block, lds, st>>>(segs, bs, k, max_nint); break;
+    case 0: fn = (const void*)k_eval<Real, 0, OTF>; break;
+    case 1: fn = (const void*)k_eval<Real, 1, OTF>; break;
+    case 2: fn = (const void*)k_eval<Real, 2, OTF>; break;
+    case 3: fn = (const void*)k_eval<Real, 3, OTF>; break;
+    case 4: fn = (const void*)k_eval<Real, 4, OTF>; break;
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  void* args[] = {(void*)&segs, (void*)&bs, (void*)&jobs, (void*)&k, (void*)&max_nint};
+  // start/stop events (when given) are recorded by the dispatch itself
+  return hipExtLaunchKernel(fn, grid, block, args, lds, st, e0, e1, 0);
 }
 
 template <typename Real>
@@ -776,29 +873,28 @@ hipError_t integrals_impl(int R, const Segment* s, const void* w, double* rec, i
 }  // namespace
 
 hipError_t launch_cache(bool fp64, int R, const Segment* s, const void* table, const void* kin, hipStream_t st) {
+  (void)hipGetLastError();
   return fp64 ? cache_impl<double>(R, s, table, kin, st) : cache_impl<float>(R, s, table, kin, st);
 }
 
-hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const int* bs, int nb, int waves,
-                       int max_nint, const void* kin, hipStream_t st) {
-  if (fp64) return otf ? eval_impl2<double, true>(R, segs, bs, nb, waves, max_nint, kin, st)
-                       : eval_impl2<double, false>(R, segs, bs, nb, waves, max_nint, kin, st);
-  return otf ? eval_impl2<float, true>(R, segs, bs, nb, waves, max_nint, kin, st)
-             : eval_impl2<float, false>(R, segs, bs, nb, waves, max_nint, kin, st);
-}
-
-hipError_t launch_finish(const Job* jobs, int n_jobs, int max_chunks, int, hipStream_t st) {
-  k_finish<<<dim3(max_chunks, n_jobs), 256, 0, st>>>(jobs);
-  return hipGetLastError();
+hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const int2* bs, const Job* jobs, int nb,
+                       int waves, int max_nint, const void* kin, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  (void)hipGetLastError();
+  if (fp64) return otf ? eval_impl2<double, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, st, e0, e1)
+                       : eval_impl2<double, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, st, e0, e1);
+  return otf ? eval_impl2<float, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, st, e0, e1)
+             : eval_impl2<float, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, st, e0, e1);
 }
 
 hipError_t launch_integrals(bool fp64, int R, const Segment* s, const void* w, double* rec, int nb, double* out,
                             hipStream_t st) {
+  (void)hipGetLastError();
   return fp64 ? integrals_impl<double>(R, s, w, rec, nb, out, st) : integrals_impl<float>(R, s, w, rec, nb, out, st);
 }
 
 hipError_t launch_eff_lookup(const double* s12, const double* s13, long long n, const float* tab, int nx, int ny,
                              double lo, double hi, double* eps, hipStream_t st) {
+  (void)hipGetLastError();
   const long long want = (n + 255) / 256;
   const int grid = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
   k_eff<<<grid, 256, 0, st>>>(s12, s13, n, tab, nx, ny, lo, hi, eps);
@@ -807,6 +903,7 @@ hipError_t launch_eff_lookup(const double* s12, const double* s13, long long n, 
 
 hipError_t launch_generate_chunk(const GenArgs& g, const void* kin, long long first, int count, double* o12,
                                  double* o13, double* of, unsigned char* oflag, int* bc, int* exc, hipStream_t st) {
+  (void)hipGetLastError();
   const Kin<double>& k = *(const Kin<double>*)kin;
   const int nb = (count + kGenBlock - 1) / kGenBlock;
   switch (g.R) {
@@ -823,6 +920,7 @@ hipError_t launch_generate_chunk(const GenArgs& g, const void* kin, long long fi
 hipError_t launch_compact(const unsigned char* flag, int count, const int* counts, int* offsets, int* total,
                           const double* a, const double* b, const double* c, double* oa, double* ob, double* oc,
                           hipStream_t st) {
+  (void)hipGetLastError();
   const int nb = (count + kGenBlock - 1) / kGenBlock;
   k_scan<<<1, 64, 0, st>>>(counts, nb, offsets, total);
   hipError_t e = hipGetLastError();

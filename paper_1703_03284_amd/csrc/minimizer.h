@@ -1,0 +1,25 @@
+// BFGS fit over a full-parameter evaluation callback; used by mipwa_fit (one context) and by the
+// serving loop (evaluations batched across jobs).  Internal.
+#pragma once
+
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace mipwa {
+
+// theta: P doubles -> f (may be +inf for an invalid or non-finite point) and the P-gradient.
+// A non-zero return aborts the fit with that status.
+using FullEval = std::function<int(const double* theta, double& f, double* grad)>;
+
+struct FitOut {
+  std::vector<double> theta, cov;  // folded theta; P x P covariance (zero rows for fixed parameters)
+  double nll = 0, edm = 0;
+  int n_iter = 0, n_eval = 0, status = 0;
+  std::string err;
+};
+
+int bfgs_fit(const FullEval& fg, int P, int N, int R, const std::vector<unsigned char>& fixed,
+             const double* theta0, double tol, int max_iter, bool hessian, double eps_rel, FitOut& out);
+
+}  // namespace mipwa

@@ -33,7 +33,7 @@ int default_blocks(int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
-  return 4 * cus;
+  return 2 * cus;
 }
 
 }  // namespace
@@ -42,20 +42,26 @@ int default_blocks(int device) {
 
 int mipwa_ctx::rebuild_launch() {
   mipwa_ctx* ctx = this;
+  const int waves = waves_cfg ? waves_cfg : (fp64 ? 4 : 8);
+  waves_eff = waves;
   const int total_tiles = ev.n_tiles + nm.n_tiles;
-  int B = std::max(2, std::min(blocks_cfg, std::max(2, total_tiles / (2 * waves_cfg))));
+  const int B = std::max(2, std::min(blocks_cfg, std::max(2, total_tiles / (2 * waves))));
   nb_d = (int)std::llround((double)B * ev.n_tiles / std::max(total_tiles, 1));
   nb_d = std::min(std::max(nb_d, 1), B - 1);
   nb_n = B - nb_d;
   n_blocks = B;
   const int nint = mh.N - 1;
   rs = record_size(nint, mh.R, otf);
-  const int rs_max = record_size(nint, mh.R, true);
-  HIPCHK(d_records.alloc((size_t)B * rs_max * sizeof(double)), "records allocation");
-  std::vector<int> bs(B);
-  for (int b = 0; b < B; ++b) bs[b] = b < nb_d ? 0 : 1;
-  HIPCHK(d_block_seg.alloc(B * sizeof(int)), "block map allocation");
-  HIPCHK(hipMemcpy(d_block_seg.p, bs.data(), B * sizeof(int), hipMemcpyHostToDevice), "block map upload");
+  const int G_d = n_groups(nb_d), G_n = n_groups(nb_n);
+  HIPCHK(d_records.alloc((size_t)B * rs * sizeof(double)), "records allocation");
+  HIPCHK(d_grec.alloc((size_t)(G_d + G_n) * rs * sizeof(double)), "group records allocation");
+  HIPCHK(d_fin.alloc(2 * (size_t)rs * sizeof(double)), "finish scratch allocation");
+  HIPCHK(d_gcount.alloc((size_t)(G_d + G_n + 1) * sizeof(unsigned)), "counter allocation");
+  HIPCHK(hipMemset(d_gcount.p, 0, (size_t)(G_d + G_n + 1) * sizeof(unsigned)), "counter reset");
+  std::vector<int2> bs(B);
+  for (int b = 0; b < B; ++b) bs[b] = b < nb_d ? int2{0, b} : int2{1, b - nb_d};
+  HIPCHK(d_block_seg.alloc(B * sizeof(int2)), "block map allocation");
+  HIPCHK(hipMemcpy(d_block_seg.p, bs.data(), B * sizeof(int2), hipMemcpyHostToDevice), "block map upload");
   Segment sg[2];
   std::memset(sg, 0, sizeof(sg));
   PointSet* ps[2] = {&ev, &nm};
@@ -72,30 +78,36 @@ int mipwa_ctx::rebuild_launch() {
     sg[k].kind = k;
     sg[k].nint = nint;
     sg[k].rs = rs;
-    sg[k].block0 = k ? nb_d : 0;
     sg[k].n_blocks = k ? nb_n : nb_d;
+    sg[k].job = 0;
+    sg[k].g0 = k ? G_d : 0;
   }
   std::memcpy(h_segs, sg, sizeof(sg));
   HIPCHK(d_segs.alloc(sizeof(sg)), "segment allocation");
   HIPCHK(hipMemcpy(d_segs.p, sg, sizeof(sg), hipMemcpyHostToDevice), "segment upload");
-  Job jb;
-  std::memset(&jb, 0, sizeof(jb));
-  jb.rec_d = sg[0].records;
-  jb.rec_n = sg[1].records;
-  jb.nb_d = nb_d;
-  jb.nb_n = nb_n;
-  jb.fin = d_fin.as<double>();
-  jb.tab64 = d_blob.as<double>() + tab64_off / sizeof(double);
-  jb.out = d_out.as<double>();
-  jb.counter = d_counter.as<unsigned int>();
-  jb.n_ev = (double)ev.n;
-  jb.c_eps = ev.c_eps;
-  jb.N = mh.N;
-  jb.R = mh.R;
-  jb.rs = rs;
-  jb.otf = otf ? 1 : 0;
-  jb.n_chunks = (2 * rs + 63) / 64;
-  HIPCHK(hipMemcpy(d_job.p, &jb, sizeof(jb), hipMemcpyHostToDevice), "job upload");
+  // job 0 writes the results into mapped pinned host memory (synchronous evaluations), job 1 into
+  // device memory (asynchronous evaluations, copied to the caller's buffer on its stream)
+  Job jb[2];
+  std::memset(jb, 0, sizeof(jb));
+  for (int k = 0; k < 2; ++k) {
+    jb[k].tab64 = d_blob.as<double>() + tab64_off / sizeof(double);
+    jb[k].consts = jb[k].tab64 + mh.P;
+    jb[k].grec = d_grec.as<double>();
+    jb[k].fin = d_fin.as<double>();
+    jb[k].gcount = d_gcount.as<unsigned int>();
+    jb[k].jcount = d_gcount.as<unsigned int>() + G_d + G_n;
+    jb[k].n_ev = (double)ev.n;
+    jb[k].c_eps = ev.c_eps;
+    jb[k].G_d = G_d;
+    jb[k].G_n = G_n;
+    jb[k].N = mh.N;
+    jb[k].R = mh.R;
+    jb[k].rs = rs;
+    jb[k].otf = otf ? 1 : 0;
+  }
+  jb[0].out = h_out_dev;
+  jb[1].out = d_out.as<double>();
+  HIPCHK(hipMemcpy(d_job.p, jb, sizeof(jb), hipMemcpyHostToDevice), "job upload");
   launch_dirty = false;
   return MIPWA_OK;
 }
@@ -103,7 +115,7 @@ int mipwa_ctx::rebuild_launch() {
 int mipwa_ctx::stage_params() {
   mipwa_ctx* ctx = this;
   // wait until the previous upload has left the pinned staging buffer
-  HIPCHK(hipEventSynchronize(ev_upload), "staging wait");
+  HIPCHK(hipEventSynchronize(ev_staged), "staging wait");
   const int nint = mh.N - 1, R = mh.R;
   std::vector<double> tab(table_words(nint, R));
   mh.poly_table(theta.data(), tab.data());
@@ -145,7 +157,20 @@ int mipwa_ctx::ensure_cache(hipStream_t st) {
   return MIPWA_OK;
 }
 
-int mipwa_ctx::enqueue_eval(hipStream_t st) {
+int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed) {
+  mipwa_ctx* ctx = this;
+  if (timed) HIPCHK(hipEventRecord(ev_t0, st), "event");
+  HIPCHK(hipMemcpyAsync(d_blob.p, h_blob.p, upload_bytes, hipMemcpyHostToDevice, st), "parameter upload");
+  if (!to_host) HIPCHK(hipEventRecord(ev_staged, st), "event");
+  HIPCHK(launch_eval(fp64, mh.R, otf, d_segs.as<Segment>(), d_block_seg.as<int2>(), d_job.as<Job>() + (to_host ? 0 : 1),
+                     n_blocks, waves_eff, mh.N - 1, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32, st,
+                     timed ? ev_t1 : nullptr, timed ? ev_t2 : nullptr),
+         "likelihood kernel");
+  if (timed) HIPCHK(hipEventRecord(ev_t3, st), "event");
+  return MIPWA_OK;
+}
+
+int mipwa_ctx::prepare_eval(hipStream_t st) {
   mipwa_ctx* ctx = this;
   if (!ev.loaded || !nm.loaded) return fail(MIPWA_E_STATE, "load events and normalisation points first");
   if (!have_theta) return fail(MIPWA_E_STATE, "set parameters first");
@@ -155,21 +180,32 @@ int mipwa_ctx::enqueue_eval(hipStream_t st) {
   }
   int rc = stage_params();
   if (rc) return rc;
-  HIPCHK(hipEventRecord(ev_t0, st), "event");
-  HIPCHK(hipMemcpyAsync(d_blob.p, h_blob.p, upload_bytes, hipMemcpyHostToDevice, st), "parameter upload");
-  HIPCHK(hipEventRecord(ev_upload, st), "event");
-  if (!otf) {
+  if (!otf && shapes_changed()) {
+    // the resonance cache needs this evaluation's shape constants on the device first
+    HIPCHK(hipMemcpyAsync(d_blob.p, h_blob.p, upload_bytes, hipMemcpyHostToDevice, st), "parameter upload");
     rc = ensure_cache(st);
     if (rc) return rc;
   }
-  HIPCHK(hipEventRecord(ev_t1, st), "event");
-  HIPCHK(launch_eval(fp64, mh.R, otf, d_segs.as<Segment>(), d_block_seg.as<int>(), n_blocks, waves_cfg, mh.N - 1,
-                     fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32, st),
-         "likelihood kernel");
-  HIPCHK(hipEventRecord(ev_t2, st), "event");
-  HIPCHK(launch_finish(d_job.as<Job>(), 1, (2 * rs + 63) / 64, mh.N, st), "reduction kernel");
-  HIPCHK(hipEventRecord(ev_t3, st), "event");
-  timing_pending = true;
+  return MIPWA_OK;
+}
+
+int mipwa_ctx::run_sync_eval() {
+  mipwa_ctx* ctx = this;
+  int rc = prepare_eval(stream);
+  if (rc) return rc;
+  rc = enqueue_kernels(stream, true, timing_on);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(stream), "stream sync");
+  if (timing_on) {
+    float a = 0, b = 0;
+    if (hipEventElapsedTime(&a, ev_t0, ev_t3) == hipSuccess && hipEventElapsedTime(&b, ev_t1, ev_t2) == hipSuccess) {
+      t_count += 1;
+      t_total += a;
+      t_stream += b;
+      timing_pending = true;
+    }
+    (void)hipGetLastError();
+  }
   return MIPWA_OK;
 }
 
@@ -213,7 +249,7 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
     delete ctx;
     return MIPWA_E_HIP;
   }
-  for (hipEvent_t* e : {&ctx->ev_upload, &ctx->ev_t0, &ctx->ev_t1, &ctx->ev_t2, &ctx->ev_t3})
+  for (hipEvent_t* e : {&ctx->ev_staged, &ctx->ev_t0, &ctx->ev_t1, &ctx->ev_t2, &ctx->ev_t3})
     if (hipEventCreate(e) != hipSuccess) {
       delete ctx;
       return MIPWA_E_HIP;
@@ -223,28 +259,32 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
   const size_t tbytes = table_words(mh.N - 1, mh.R) * real;
   ctx->tab64_off = (tbytes + 255) / 256 * 256;
   ctx->upload_bytes = ctx->tab64_off + mh.P * sizeof(double);
-  const size_t blob = ctx->tab64_off + ((size_t)mh.P + (size_t)mh.N * mh.N + mh.N) * sizeof(double);
+  const size_t blob = ctx->tab64_off + ((size_t)mh.P + 2 * (size_t)mh.N + mh.N) * sizeof(double);
   if (ctx->d_blob.alloc(blob) != hipSuccess || ctx->h_blob.alloc(ctx->upload_bytes) != hipSuccess ||
-      ctx->d_fin.alloc(2 * record_size(mh.N - 1, mh.R, true) * sizeof(double)) != hipSuccess ||
-      ctx->d_counter.alloc(64) != hipSuccess || ctx->d_out.alloc((1 + mh.P) * sizeof(double)) != hipSuccess ||
-      ctx->h_out.alloc((1 + mh.P) * sizeof(double)) != hipSuccess || ctx->d_job.alloc(sizeof(Job)) != hipSuccess) {
+      ctx->d_out.alloc((1 + mh.P) * sizeof(double)) != hipSuccess ||
+      ctx->h_out.alloc((1 + mh.P) * sizeof(double), true) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&ctx->h_out_dev, ctx->h_out.p, 0) != hipSuccess ||
+      ctx->d_job.alloc(2 * sizeof(Job)) != hipSuccess) {
     delete ctx;
     return MIPWA_E_NOMEM;
   }
-  // constant part of the FP64 table: K^T and h after theta
-  std::vector<double> cst((size_t)mh.N * mh.N + mh.N - 1);
-  std::copy(mh.KT.begin(), mh.KT.end(), cst.begin());
-  std::copy(mh.h.begin(), mh.h.end(), cst.begin() + (size_t)mh.N * mh.N);
+  // constant part of the FP64 table after theta: Thomas factors of the interior spline system, h
+  const int ni = mh.N - 2;
+  std::vector<double> cst(2 * (size_t)ni + mh.N - 1);
+  for (int i = 0; i < ni; ++i) {
+    cst[i] = mh.th_c[i];
+    cst[ni + i] = 1.0 / mh.th_d[i];
+  }
+  std::copy(mh.h.begin(), mh.h.end(), cst.begin() + 2 * ni);
   if (hipMemcpy(ctx->d_blob.as<char>() + ctx->tab64_off + mh.P * sizeof(double), cst.data(),
-                cst.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(ctx->d_counter.p, 0, 64) != hipSuccess || hipEventRecord(ctx->ev_upload, ctx->stream) != hipSuccess) {
+                cst.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     delete ctx;
     return MIPWA_E_HIP;
   }
   ctx->fixed.assign(mh.P, 0);
   for (int p = 2 * mh.N + 2 * mh.R; p < mh.P; ++p) ctx->fixed[p] = 1;
   ctx->blocks_cfg = default_blocks(device);
-  ctx->waves_cfg = 4;
+  ctx->waves_cfg = 0;
   *out = ctx;
   return MIPWA_OK;
 }
@@ -264,7 +304,7 @@ int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves) {
   if (!ctx) return MIPWA_E_INVAL;
   if (blocks < 0 || waves < 0 || waves > 8) return ctx->fail(MIPWA_E_INVAL, "waves per block must be 1..8");
   ctx->blocks_cfg = blocks ? blocks : default_blocks(ctx->device);
-  ctx->waves_cfg = waves ? waves : 4;
+  ctx->waves_cfg = waves;  // 0: 8 waves per block for FP32 streams, 4 for FP64
   ctx->launch_dirty = true;
   return MIPWA_OK;
 }
@@ -333,11 +373,8 @@ int mipwa_set_params(mipwa_ctx* ctx, const double* theta, int n) {
 int mipwa_eval(mipwa_ctx* ctx, double* nll, double* grad) {
   if (!ctx) return MIPWA_E_INVAL;
   (void)hipSetDevice(ctx->device);
-  int rc = ctx->enqueue_eval(ctx->stream);
+  int rc = ctx->run_sync_eval();
   if (rc) return rc;
-  const size_t bytes = (1 + ctx->mh.P) * sizeof(double);
-  HIPCHK(hipMemcpyAsync(ctx->h_out.p, ctx->d_out.p, bytes, hipMemcpyDeviceToHost, ctx->stream), "result copy");
-  HIPCHK(hipStreamSynchronize(ctx->stream), "stream sync");
   const double* o = ctx->h_out.as<double>();
   if (nll) *nll = o[0];
   if (grad) std::memcpy(grad, o + 1, ctx->mh.P * sizeof(double));
@@ -353,8 +390,11 @@ int mipwa_eval_async(mipwa_ctx* ctx, void* stream, double* d_out) {
   if (!d_out) return ctx->fail(MIPWA_E_INVAL, "d_out is NULL");
   (void)hipSetDevice(ctx->device);
   hipStream_t st = (hipStream_t)stream;
-  int rc = ctx->enqueue_eval(st);
+  int rc = ctx->prepare_eval(st);
   if (rc) return rc;
+  rc = ctx->enqueue_kernels(st, false, true);
+  if (rc) return rc;
+  ctx->timing_pending = true;
   HIPCHK(hipMemcpyAsync(d_out, ctx->d_out.p, (1 + ctx->mh.P) * sizeof(double), hipMemcpyDeviceToDevice, st),
          "result copy");
   return MIPWA_OK;
@@ -366,10 +406,27 @@ int mipwa_last_timing(const mipwa_ctx* cctx, double* total_ms, double* stream_ms
   if (!ctx->timing_pending) return ctx->fail(MIPWA_E_STATE, "no evaluation timed yet");
   HIPCHK(hipEventSynchronize(ctx->ev_t3), "event sync");
   float a = 0, b = 0;
-  HIPCHK(hipEventElapsedTime(&a, ctx->ev_upload, ctx->ev_t3), "event time");
+  HIPCHK(hipEventElapsedTime(&a, ctx->ev_t0, ctx->ev_t3), "event time");
   HIPCHK(hipEventElapsedTime(&b, ctx->ev_t1, ctx->ev_t2), "event time");
   if (total_ms) *total_ms = a;
   if (stream_ms) *stream_ms = b;
+  return MIPWA_OK;
+}
+
+int mipwa_set_timing(mipwa_ctx* ctx, int on) {
+  if (!ctx) return MIPWA_E_INVAL;
+  ctx->timing_on = on != 0;
+  ctx->t_count = 0;
+  ctx->t_total = ctx->t_stream = 0.0;
+  return MIPWA_OK;
+}
+
+int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_ms, double* mean_stream_ms) {
+  if (!ctx) return MIPWA_E_INVAL;
+  const double n = ctx->t_count > 0 ? (double)ctx->t_count : 1.0;
+  if (count) *count = ctx->t_count;
+  if (mean_total_ms) *mean_total_ms = ctx->t_total / n;
+  if (mean_stream_ms) *mean_stream_ms = ctx->t_stream / n;
   return MIPWA_OK;
 }
 
@@ -387,7 +444,7 @@ int mipwa_integrals(mipwa_ctx* ctx, int with_eff, double* Ijk) {
   int rc = ctx->stage_params();
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(ctx->d_blob.p, ctx->h_blob.p, ctx->upload_bytes, hipMemcpyHostToDevice, st), "upload");
-  HIPCHK(hipEventRecord(ctx->ev_upload, st), "event");
+  HIPCHK(hipEventRecord(ctx->ev_staged, st), "event");
   // the normalisation segment with its cache valid at the current shapes
   Segment sg;
   std::memset(&sg, 0, sizeof(sg));

@@ -1,0 +1,708 @@
+// Toy-fit serving with continuous batching.
+//
+// Each submitted job is a maximum-likelihood fit (the fit of Sec. 2 / Sec. 4 on a toy sample) of its
+// own events against a normalisation sample shared by the server.  Jobs wait in a queue until their
+// device footprint fits the HBM budget; an admitted job loads its events (cell sort, resonance cache)
+// on its own stream and thread, then runs the BFGS fit in that thread.  Every evaluation it asks for
+// is posted to the scheduler, which gathers the pending evaluations of all active jobs into one launch
+// of the streaming kernel (one data segment and one normalisation segment per job; the normalisation
+// segments of jobs sharing a knot grid read the same point arrays, and their blocks are interleaved
+// so that the same tiles are read close together in time).  Jobs that become active while a step
+// runs join the next step.  A job's block count depends only on its own sizes, so its reduction
+// order, and therefore its result, is bitwise the same alone or in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "engine.h"
+#include "host.h"
+#include "minimizer.h"
+#include "mipwa.h"
+
+using namespace mipwa;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr int kServeWaves = 8;
+constexpr int kMaxSegBlocks = 256;
+
+int seg_blocks(int n_tiles) {
+  const int b = (n_tiles + 2 * kServeWaves - 1) / (2 * kServeWaves);
+  return std::min(std::max(b, 1), kMaxSegBlocks);
+}
+
+struct NormSet {
+  std::vector<double> key;  // kinematics, knots, resonance constants and shapes
+  ModelHost mh;
+  PointSet ps;
+  int nb = 0;
+  size_t bytes = 0;
+};
+
+enum JobState { QUEUED, LOADING, ACTIVE, FINISHED };
+
+struct SJob {
+  int64_t id = 0;
+  ModelHost mh;
+  std::vector<double> s12, s13;
+  long long n = 0;
+  std::vector<double> theta0;
+  std::vector<unsigned char> fixed;
+  double tol = 1e-4;
+  int max_iter = 1000;
+  bool hessian = false;
+  PointSet ev;
+  NormSet* norm = nullptr;
+  int nb_d = 0, G_d = 0, G_n = 0, rs = 0;
+  DevBuf d_rec, d_grec, d_fin, d_cnt, d_consts, d_tab;
+  size_t bytes = 0;
+  JobState state = QUEUED;
+  int status = MIPWA_OK;
+  bool cancel = false;
+  std::string err;
+  Clock::time_point t_submit, t_done;
+  std::thread worker;
+  // one outstanding evaluation request
+  bool req = false, inflight = false, done = false;
+  std::vector<char> staged;  // [Real table | pad to 256 | theta (P doubles)]
+  double f = 0;
+  std::vector<double> g;
+  std::condition_variable cv;
+  FitOut result;
+};
+
+std::vector<double> norm_key(const ModelHost& mh, const std::vector<double>& theta) {
+  std::vector<double> k = {mh.M, mh.m1, mh.m2, mh.m3, mh.rD, (double)mh.N, (double)mh.R};
+  k.insert(k.end(), mh.knots.begin(), mh.knots.end());
+  for (int r = 0; r < mh.R; ++r) {
+    k.push_back(mh.res[r].spin);
+    k.push_back(mh.res[r].radius);
+    k.push_back(theta[2 * mh.N + 2 * mh.R + 2 * r]);
+    k.push_back(theta[2 * mh.N + 2 * mh.R + 2 * r + 1]);
+  }
+  return k;
+}
+
+size_t staged_bytes(const ModelHost& mh, bool fp64, size_t* theta_off) {
+  const size_t t = table_words(mh.N - 1, mh.R) * (fp64 ? 8 : 4);
+  *theta_off = (t + 255) / 256 * 256;
+  return *theta_off + (size_t)mh.P * 8;
+}
+
+// evaluation table (working precision) and theta (FP64) for one job at theta
+void stage(const ModelHost& mh, bool fp64, const double* theta, std::vector<char>& out) {
+  size_t toff = 0;
+  out.assign(staged_bytes(mh, fp64, &toff), 0);
+  const int nint = mh.N - 1, R = mh.R;
+  std::vector<double> tab(table_words(nint, R));
+  mh.poly_table(theta, tab.data());
+  for (int r = 0; r < R; ++r) {
+    const double cm = theta[2 * mh.N + 2 * r], ca = theta[2 * mh.N + 2 * r + 1];
+    tab[8 * nint + 2 * r] = cm * std::cos(ca);
+    tab[8 * nint + 2 * r + 1] = cm * std::sin(ca);
+  }
+  mh.res_table(theta, tab.data() + 8 * nint + 2 * R);
+  if (fp64) {
+    std::memcpy(out.data(), tab.data(), tab.size() * 8);
+  } else {
+    float* f = reinterpret_cast<float*>(out.data());
+    for (size_t i = 0; i < tab.size(); ++i) f[i] = (float)tab[i];
+  }
+  std::memcpy(out.data() + toff, theta, (size_t)mh.P * 8);
+}
+
+Segment cache_segment(const PointSet& ps, int nint) {
+  Segment sg;
+  std::memset(&sg, 0, sizeof(sg));
+  sg.ss = ps.ss.p;
+  sg.cache = ps.cache.p;
+  sg.n = ps.n;
+  sg.nint = nint;
+  return sg;
+}
+
+}  // namespace
+
+struct mipwa_server {
+  int device = 0;
+  bool fp64 = false;
+  size_t budget = 0;
+  hipStream_t stream = nullptr;
+  std::mutex mu;       // all job and queue state
+  std::mutex norm_mu;  // creation of shared normalisation sets
+  std::condition_variable cv_sched, cv_done;
+  std::thread sched;
+  bool stop = false;
+  std::vector<double> n12, n13, nw;
+  std::vector<std::unique_ptr<NormSet>> norms;
+  std::map<int64_t, std::unique_ptr<SJob>> jobs;
+  std::deque<SJob*> queue;
+  int64_t next_id = 1;
+  size_t used = 0, peak = 0;
+  int running = 0;  // LOADING + ACTIVE
+  long long steps = 0;
+  double batch_sum = 0;
+  bool any_submit = false;
+  Clock::time_point t_first_submit, t_last_done;
+  std::vector<double> latencies;
+  HostBuf h_batch, h_res;
+  DevBuf d_batch;
+  double* h_res_dev = nullptr;
+  std::string err;
+
+  int fail(int code, const std::string& m) {
+    err = m;
+    return code;
+  }
+};
+
+static void serve_worker(mipwa_server* S, SJob* J);
+
+namespace {
+
+void admit(mipwa_server* S) {
+  while (!S->queue.empty()) {
+    SJob* J = S->queue.front();
+    if (J->cancel) {
+      S->queue.pop_front();
+      J->state = FINISHED;
+      J->status = MIPWA_E_CANCELLED;
+      S->cv_done.notify_all();
+      continue;
+    }
+    if (S->running > 0 && S->used + J->bytes > S->budget) break;
+    S->queue.pop_front();
+    S->used += J->bytes;
+    S->peak = std::max(S->peak, S->used);
+    S->running += 1;
+    J->state = LOADING;
+    J->worker = std::thread(serve_worker, S, J);
+  }
+}
+
+NormSet* get_norm(mipwa_server* S, const ModelHost& mh, const std::vector<double>& theta, hipStream_t st,
+                  std::string& err, int& rc) {
+  std::lock_guard<std::mutex> g(S->norm_mu);
+  const std::vector<double> key = norm_key(mh, theta);
+  for (auto& ns : S->norms)
+    if (ns->key == key) return ns.get();
+  auto ns = std::make_unique<NormSet>();
+  ns->key = key;
+  ns->mh = mh;
+  EffTable none;
+  rc = load_points(mh, S->fp64, 1, S->n12.data(), S->n13.data(), S->nw.data(), nullptr, (long long)S->n12.size(),
+                   none, st, ns->ps, err);
+  if (rc) return nullptr;
+  std::vector<char> tab;
+  stage(mh, S->fp64, theta.data(), tab);
+  DevBuf dt;
+  Segment sg = cache_segment(ns->ps, mh.N - 1);
+  if (dt.alloc(tab.size()) != hipSuccess || hipMemcpy(dt.p, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      launch_cache(S->fp64, mh.R, &sg, dt.p, S->fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    err = "normalisation cache build failed";
+    rc = MIPWA_E_HIP;
+    return nullptr;
+  }
+  const size_t real = S->fp64 ? 8 : 4;
+  ns->nb = seg_blocks(ns->ps.n_tiles);
+  ns->bytes = (size_t)ns->ps.n * (6 + 2 * mh.R) * real + (size_t)ns->ps.n_tiles * sizeof(Tile);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->used += ns->bytes;
+    S->peak = std::max(S->peak, S->used);
+  }
+  S->norms.push_back(std::move(ns));
+  return S->norms.back().get();
+}
+
+void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  J->state = FINISHED;
+  J->status = status;
+  J->err = err;
+  J->t_done = Clock::now();
+  if (status == MIPWA_OK || status == MIPWA_E_NOCONV) {
+    S->latencies.push_back(std::chrono::duration<double>(J->t_done - J->t_submit).count());
+    S->t_last_done = J->t_done;
+  }
+  J->ev = PointSet();
+  J->d_rec.release();
+  J->d_grec.release();
+  J->d_fin.release();
+  J->d_cnt.release();
+  J->d_consts.release();
+  S->used -= J->bytes;
+  S->running -= 1;
+  S->cv_done.notify_all();
+  S->cv_sched.notify_all();
+}
+
+}  // namespace
+
+static void serve_worker(mipwa_server* S, SJob* J) {
+  (void)hipSetDevice(S->device);
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    finish_job(S, J, MIPWA_E_HIP, "stream creation failed");
+    return;
+  }
+  std::string err;
+  EffTable none;
+  int rc = load_points(J->mh, S->fp64, 0, J->s12.data(), J->s13.data(), nullptr, nullptr, J->n, none, st, J->ev, err);
+  J->s12 = std::vector<double>();
+  J->s13 = std::vector<double>();
+  NormSet* ns = nullptr;
+  if (!rc) ns = get_norm(S, J->mh, J->theta0, st, err, rc);
+  if (!rc) {
+    // resonance cache of the events at the job's (fixed) shapes; per-job reduction scratch
+    std::vector<char> tab;
+    stage(J->mh, S->fp64, J->theta0.data(), tab);
+    Segment sg = cache_segment(J->ev, J->mh.N - 1);
+    J->norm = ns;
+    J->nb_d = seg_blocks(J->ev.n_tiles);
+    J->G_d = n_groups(J->nb_d);
+    J->G_n = n_groups(ns->nb);
+    J->rs = record_size(J->mh.N - 1, J->mh.R, false);
+    const int ni = J->mh.N - 2;
+    std::vector<double> cst(2 * (size_t)ni + J->mh.N - 1);
+    for (int i = 0; i < ni; ++i) {
+      cst[i] = J->mh.th_c[i];
+      cst[ni + i] = 1.0 / J->mh.th_d[i];
+    }
+    std::copy(J->mh.h.begin(), J->mh.h.end(), cst.begin() + 2 * ni);
+    const size_t cnt = (size_t)(J->G_d + J->G_n + 1) * sizeof(unsigned);
+    if (J->d_tab.alloc(tab.size()) || J->d_rec.alloc((size_t)(J->nb_d + ns->nb) * J->rs * 8) ||
+        J->d_grec.alloc((size_t)(J->G_d + J->G_n) * J->rs * 8) || J->d_fin.alloc(2 * (size_t)J->rs * 8) ||
+        J->d_cnt.alloc(cnt) || J->d_consts.alloc(cst.size() * 8)) {
+      rc = MIPWA_E_NOMEM;
+      err = "device allocation for a job failed";
+    } else if (hipMemcpy(J->d_tab.p, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemset(J->d_cnt.p, 0, cnt) != hipSuccess ||
+               launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.p,
+                            S->fp64 ? (const void*)&J->mh.kin64 : (const void*)&J->mh.kin32, st) != hipSuccess ||
+               hipStreamSynchronize(st) != hipSuccess) {
+      rc = MIPWA_E_HIP;
+      err = "loading a job failed";
+    }
+    J->d_tab.release();
+  }
+  (void)hipStreamDestroy(st);
+  if (rc) {
+    finish_job(S, J, rc, err);
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    J->state = ACTIVE;
+    S->cv_sched.notify_all();
+  }
+  const ModelHost& mh = J->mh;
+  FullEval fg = [S, J, &mh](const double* th, double& f, double* g) -> int {
+    std::string e;
+    if (mh.check_theta(th, e) != MIPWA_OK) {
+      f = INFINITY;
+      return MIPWA_OK;
+    }
+    std::vector<char> staged;
+    stage(mh, S->fp64, th, staged);
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (J->cancel || S->stop) return MIPWA_E_CANCELLED;
+    J->staged.swap(staged);
+    J->req = true;
+    J->done = false;
+    S->cv_sched.notify_all();
+    J->cv.wait(lk, [&] { return J->done || ((J->cancel || S->stop) && !J->inflight); });
+    if (!J->done) return MIPWA_E_CANCELLED;
+    f = std::isfinite(J->f) ? J->f : INFINITY;
+    std::copy(J->g.begin(), J->g.end(), g);
+    return MIPWA_OK;
+  };
+  FitOut out;
+  rc = bfgs_fit(fg, mh.P, mh.N, mh.R, J->fixed, J->theta0.data(), J->tol, J->max_iter, J->hessian,
+                S->fp64 ? 1e-13 : 1e-10, out);
+  J->result = out;
+  finish_job(S, J, rc ? rc : out.status, out.err);
+}
+
+namespace {
+
+// One batched step: every job in `batch` (same resonance count) evaluated in one launch.
+int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
+  std::map<int, std::vector<SJob*>> by_r;
+  for (SJob* J : batch) by_r[J->mh.R].push_back(J);
+  // results (mapped host memory) for every job of the step
+  size_t res_total = 0;
+  std::map<SJob*, size_t> res_of;
+  for (SJob* J : batch) {
+    res_of[J] = res_total;
+    res_total += 1 + J->mh.P;
+  }
+  if (S->h_res.bytes < res_total * 8) {
+    if (S->h_res.alloc(res_total * 8 * 2, true) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&S->h_res_dev, S->h_res.p, 0) != hipSuccess)
+      return S->fail(MIPWA_E_NOMEM, "result buffer allocation failed");
+  }
+  for (auto& kv : by_r) {
+    const int R = kv.first;
+    std::vector<SJob*>& js = kv.second;
+    const int nj = (int)js.size();
+    // block map: data segments job-major, then normalisation segments interleaved by block index
+    // among the jobs sharing a normalisation set
+    std::vector<int2> map;
+    for (int j = 0; j < nj; ++j)
+      for (int b = 0; b < js[j]->nb_d; ++b) map.push_back(int2{2 * j, b});
+    std::map<NormSet*, std::vector<int>> by_norm;
+    for (int j = 0; j < nj; ++j) by_norm[js[j]->norm].push_back(j);
+    for (auto& nk : by_norm)
+      for (int b = 0; b < nk.first->nb; ++b)
+        for (int j : nk.second) map.push_back(int2{2 * j + 1, b});
+    // layout of the step's upload
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off = (off + bytes + 255) / 256 * 256;
+      return o;
+    };
+    const size_t o_map = take(map.size() * sizeof(int2));
+    const size_t o_seg = take((size_t)2 * nj * sizeof(Segment));
+    const size_t o_job = take((size_t)nj * sizeof(Job));
+    std::vector<size_t> o_tab(nj), o_th(nj);
+    int max_nint = 1;
+    for (int j = 0; j < nj; ++j) {
+      size_t toff = 0;
+      const size_t bytes = staged_bytes(js[j]->mh, S->fp64, &toff);
+      o_tab[j] = take(bytes);
+      o_th[j] = o_tab[j] + toff;
+      max_nint = std::max(max_nint, js[j]->mh.N - 1);
+    }
+    if (S->h_batch.alloc(off) != hipSuccess || S->d_batch.alloc(off) != hipSuccess)
+      return S->fail(MIPWA_E_NOMEM, "batch buffer allocation failed");
+    char* hb = S->h_batch.as<char>();
+    char* db = S->d_batch.as<char>();
+    std::memcpy(hb + o_map, map.data(), map.size() * sizeof(int2));
+    Segment* sg = reinterpret_cast<Segment*>(hb + o_seg);
+    Job* jb = reinterpret_cast<Job*>(hb + o_job);
+    std::memset(sg, 0, (size_t)2 * nj * sizeof(Segment));
+    std::memset(jb, 0, (size_t)nj * sizeof(Job));
+    for (int j = 0; j < nj; ++j) {
+      SJob* J = js[j];
+      std::memcpy(hb + o_tab[j], J->staged.data(), J->staged.size());
+      const PointSet* ps[2] = {&J->ev, &J->norm->ps};
+      const int nbs[2] = {J->nb_d, J->norm->nb};
+      for (int k = 0; k < 2; ++k) {
+        Segment& s = sg[2 * j + k];
+        s.tt = ps[k]->tt.p;
+        s.ss = ps[k]->ss.p;
+        s.w = k ? ps[k]->w.p : nullptr;
+        s.cache = ps[k]->cache.p;
+        s.tiles = ps[k]->tiles.as<Tile>();
+        s.table = db + o_tab[j];
+        s.records = J->d_rec.as<double>() + (size_t)(k ? J->nb_d : 0) * J->rs;
+        s.n = ps[k]->n;
+        s.n_tiles = ps[k]->n_tiles;
+        s.kind = k;
+        s.nint = J->mh.N - 1;
+        s.rs = J->rs;
+        s.n_blocks = nbs[k];
+        s.job = j;
+        s.g0 = k ? J->G_d : 0;
+      }
+      Job& q = jb[j];
+      q.tab64 = reinterpret_cast<const double*>(db + o_th[j]);
+      q.consts = J->d_consts.as<double>();
+      q.out = S->h_res_dev + res_of[J];
+      q.grec = J->d_grec.as<double>();
+      q.fin = J->d_fin.as<double>();
+      q.gcount = J->d_cnt.as<unsigned int>();
+      q.jcount = J->d_cnt.as<unsigned int>() + J->G_d + J->G_n;
+      q.n_ev = (double)J->ev.n;
+      q.c_eps = 0.0;
+      q.G_d = J->G_d;
+      q.G_n = J->G_n;
+      q.N = J->mh.N;
+      q.R = J->mh.R;
+      q.rs = J->rs;
+      q.otf = 0;
+    }
+    if (hipMemcpyAsync(db, hb, off, hipMemcpyHostToDevice, S->stream) != hipSuccess)
+      return S->fail(MIPWA_E_HIP, "batch upload failed");
+    const ModelHost& mh0 = js[0]->mh;
+    if (launch_eval(S->fp64, R, false, reinterpret_cast<const Segment*>(db + o_seg),
+                    reinterpret_cast<const int2*>(db + o_map), reinterpret_cast<const Job*>(db + o_job),
+                    (int)map.size(), kServeWaves, max_nint,
+                    S->fp64 ? (const void*)&mh0.kin64 : (const void*)&mh0.kin32, S->stream) != hipSuccess)
+      return S->fail(MIPWA_E_HIP, "batched likelihood kernel failed");
+    if (hipStreamSynchronize(S->stream) != hipSuccess) return S->fail(MIPWA_E_HIP, "batch sync failed");
+  }
+  const double* res = S->h_res.as<double>();
+  for (SJob* J : batch) {
+    const double* o = res + res_of[J];
+    J->f = o[0];
+    J->g.assign(o + 1, o + 1 + J->mh.P);
+  }
+  return MIPWA_OK;
+}
+
+void sched_loop(mipwa_server* S) {
+  (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  while (!S->stop) {
+    admit(S);
+    auto n_pending = [&] {
+      int p = 0, a = 0;
+      for (auto& kv : S->jobs) {
+        SJob* J = kv.second.get();
+        if (J->state != ACTIVE) continue;
+        ++a;
+        if (J->req && !J->inflight && !J->cancel) ++p;
+      }
+      return std::make_pair(p, a);
+    };
+    for (auto& kv : S->jobs)
+      if (kv.second->state == FINISHED && kv.second->worker.joinable()) kv.second->worker.join();
+    auto admissible = [&] {
+      if (S->queue.empty()) return false;
+      SJob* J = S->queue.front();
+      return J->cancel || S->running == 0 || S->used + J->bytes <= S->budget;
+    };
+    S->cv_sched.wait(lk, [&] { return S->stop || n_pending().first > 0 || admissible(); });
+    if (S->stop) break;
+    if (n_pending().first == 0) continue;
+    if (S->stop) break;
+    // batching window: until every active job has asked, or 2 ms after the first request
+    const auto deadline = Clock::now() + std::chrono::milliseconds(2);
+    while (!S->stop) {
+      auto pa = n_pending();
+      if (pa.first >= pa.second) break;
+      if (S->cv_sched.wait_until(lk, deadline) == std::cv_status::timeout) break;
+    }
+    if (S->stop) break;
+    std::vector<SJob*> batch;
+    for (auto& kv : S->jobs) {
+      SJob* J = kv.second.get();
+      if (J->state == ACTIVE && J->req && !J->inflight && !J->cancel) {
+        J->inflight = true;
+        batch.push_back(J);
+      }
+    }
+    if (batch.empty()) continue;
+    lk.unlock();
+    const int rc = run_batch(S, batch);
+    lk.lock();
+    for (SJob* J : batch) {
+      if (rc) J->f = NAN;
+      J->req = false;
+      J->inflight = false;
+      J->done = true;
+      J->cv.notify_all();
+    }
+    S->steps += 1;
+    S->batch_sum += (double)batch.size();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mipwa_server_create(int device, int precision, size_t budget, mipwa_server** out) {
+  if (!out || (precision != MIPWA_FP64 && precision != MIPWA_MIXED)) return MIPWA_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MIPWA_E_INVAL;
+  auto S = new (std::nothrow) mipwa_server();
+  if (!S) return MIPWA_E_NOMEM;
+  S->device = device;
+  S->fp64 = precision == MIPWA_FP64;
+  (void)hipSetDevice(device);
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)64 << 30;
+  S->budget = budget ? budget : (size_t)(0.8 * (double)free_b);
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete S;
+    return MIPWA_E_HIP;
+  }
+  S->sched = std::thread(sched_loop, S);
+  *out = S;
+  return MIPWA_OK;
+}
+
+int mipwa_server_set_norm(mipwa_server* S, const double* s12, const double* s13, const double* w, int64_t n) {
+  if (!S) return MIPWA_E_INVAL;
+  if (!s12 || !s13 || !w || n < 1) return S->fail(MIPWA_E_INVAL, "need n >= 1 normalisation points with weights");
+  std::lock_guard<std::mutex> g(S->norm_mu);
+  if (!S->norms.empty()) return S->fail(MIPWA_E_STATE, "the normalisation sample is already in use");
+  S->n12.assign(s12, s12 + n);
+  S->n13.assign(s13, s13 + n);
+  S->nw.assign(w, w + n);
+  return MIPWA_OK;
+}
+
+int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double* s12, const double* s13, int64_t n,
+                        const double* theta0, const unsigned char* fixed, const mipwa_fit_opts* opts,
+                        int64_t* job_id) {
+  if (!S) return MIPWA_E_INVAL;
+  if (S->n12.empty()) return S->fail(MIPWA_E_STATE, "set the normalisation sample first");
+  if (!s12 || !s13 || n < 1 || !theta0 || !job_id) return S->fail(MIPWA_E_INVAL, "need events, theta0 and job_id");
+  auto J = std::make_unique<SJob>();
+  std::string err;
+  int rc = J->mh.init(model, err);
+  if (rc) return S->fail(rc, err);
+  const int P = J->mh.P, N = J->mh.N, R = J->mh.R;
+  rc = J->mh.check_theta(theta0, err);
+  if (rc) return S->fail(rc, err);
+  J->fixed.assign(P, 0);
+  if (fixed) {
+    J->fixed.assign(fixed, fixed + P);
+  } else {
+    if (R > 0) J->fixed[2 * N] = J->fixed[2 * N + 1] = 1;
+    for (int p = 2 * N + 2 * R; p < P; ++p) J->fixed[p] = 1;
+  }
+  for (int p = 2 * N + 2 * R; p < P; ++p)
+    if (!J->fixed[p]) return S->fail(MIPWA_E_INVAL, "serving jobs keep masses and widths fixed");
+  J->s12.assign(s12, s12 + n);
+  J->s13.assign(s13, s13 + n);
+  J->n = n;
+  J->theta0.assign(theta0, theta0 + P);
+  J->tol = opts && opts->tol_edm > 0 ? opts->tol_edm : 1e-4;
+  J->max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 1000;
+  J->hessian = opts ? opts->hessian != 0 : false;
+  const size_t real = S->fp64 ? 8 : 4;
+  J->bytes = (size_t)n * (4 + 2 * R) * real + (size_t)(n / kTile + 1) * 2 * sizeof(Tile) +
+             (size_t)(2 * kMaxSegBlocks + 32) * record_size(N - 1, R, false) * 8;
+  if (J->bytes > S->budget) return S->fail(MIPWA_E_NOMEM, "the job alone exceeds the HBM budget");
+  std::lock_guard<std::mutex> lk(S->mu);
+  J->id = S->next_id++;
+  J->t_submit = Clock::now();
+  if (!S->any_submit) {
+    S->any_submit = true;
+    S->t_first_submit = J->t_submit;
+  }
+  *job_id = J->id;
+  S->queue.push_back(J.get());
+  S->jobs[J->id] = std::move(J);
+  S->cv_sched.notify_all();
+  return MIPWA_OK;
+}
+
+namespace {
+int copy_result(mipwa_server* S, SJob* J, double* theta_out, mipwa_fit_info* info, double* latency) {
+  if (J->state != FINISHED) return MIPWA_E_BUSY;
+  if (J->status == MIPWA_E_CANCELLED) return MIPWA_E_CANCELLED;
+  if (J->status != MIPWA_OK && J->status != MIPWA_E_NOCONV) return S->fail(J->status, J->err);
+  if (theta_out) std::copy(J->result.theta.begin(), J->result.theta.end(), theta_out);
+  if (info) {
+    info->nll = J->result.nll;
+    info->edm = J->result.edm;
+    info->n_iter = J->result.n_iter;
+    info->n_eval = J->result.n_eval;
+    info->status = J->status;
+  }
+  if (latency) *latency = std::chrono::duration<double>(J->t_done - J->t_submit).count();
+  return J->status;
+}
+}  // namespace
+
+int mipwa_server_poll(mipwa_server* S, int64_t id, double* theta_out, mipwa_fit_info* info, double* latency_s) {
+  if (!S) return MIPWA_E_INVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(id);
+  if (it == S->jobs.end()) return S->fail(MIPWA_E_INVAL, "unknown job");
+  return copy_result(S, it->second.get(), theta_out, info, latency_s);
+}
+
+int mipwa_server_wait(mipwa_server* S, int64_t id, double timeout_s, double* theta_out, mipwa_fit_info* info,
+                      double* latency_s) {
+  if (!S) return MIPWA_E_INVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(id);
+  if (it == S->jobs.end()) return S->fail(MIPWA_E_INVAL, "unknown job");
+  SJob* J = it->second.get();
+  auto ready = [&] { return J->state == FINISHED; };
+  if (timeout_s > 0)
+    S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
+  else
+    S->cv_done.wait(lk, ready);
+  return copy_result(S, J, theta_out, info, latency_s);
+}
+
+int mipwa_server_cancel(mipwa_server* S, int64_t id) {
+  if (!S) return MIPWA_E_INVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(id);
+  if (it == S->jobs.end()) return S->fail(MIPWA_E_INVAL, "unknown job");
+  SJob* J = it->second.get();
+  J->cancel = true;
+  J->cv.notify_all();
+  S->cv_sched.notify_all();
+  return MIPWA_OK;
+}
+
+int mipwa_server_stats(mipwa_server* S, mipwa_serve_stats* st) {
+  if (!S || !st) return MIPWA_E_INVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::memset(st, 0, sizeof(*st));
+  std::vector<double> lat = S->latencies;
+  std::sort(lat.begin(), lat.end());
+  auto pct = [&](double q) {
+    if (lat.empty()) return 0.0;
+    const double pos = q * (lat.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - i;
+    return i + 1 < lat.size() ? lat[i] * (1 - f) + lat[i + 1] * f : lat[i];
+  };
+  st->n_done = (int64_t)lat.size();
+  st->p50_s = pct(0.50);
+  st->p99_s = pct(0.99);
+  const double span = std::chrono::duration<double>(S->t_last_done - S->t_first_submit).count();
+  st->fits_per_s = span > 0 ? lat.size() / span : 0.0;
+  for (auto& kv : S->jobs) {
+    if (kv.second->state == QUEUED) st->n_queued += 1;
+    if (kv.second->state == LOADING || kv.second->state == ACTIVE) st->n_active += 1;
+  }
+  st->peak_bytes = (int64_t)S->peak;
+  st->steps = S->steps;
+  st->mean_batch = S->steps ? S->batch_sum / S->steps : 0.0;
+  return MIPWA_OK;
+}
+
+const char* mipwa_server_last_error(const mipwa_server* S) { return S ? S->err.c_str() : "server is NULL"; }
+
+void mipwa_server_destroy(mipwa_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    for (auto& kv : S->jobs) {
+      kv.second->cancel = true;
+      kv.second->cv.notify_all();
+    }
+    S->cv_sched.notify_all();
+  }
+  if (S->sched.joinable()) S->sched.join();
+  for (auto& kv : S->jobs)
+    if (kv.second->worker.joinable()) kv.second->worker.join();
+  (void)hipSetDevice(S->device);
+  (void)hipStreamSynchronize(S->stream);
+  S->jobs.clear();
+  S->norms.clear();
+  (void)hipStreamDestroy(S->stream);
+  delete S;
+}
+
+}  // extern "C"

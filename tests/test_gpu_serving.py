@@ -1,0 +1,117 @@
+"""Toy-fit serving: continuous batching, admission by HBM footprint, isolation between jobs."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import generate as OG
+from oracle import kinematics as K
+from tests.conftest import oracle_model
+
+pytestmark = pytest.mark.gpu
+
+
+def _toy(n, n_knots, seed, wl=synth.C1):
+    kn = synth.uniform_knots(wl.decay, n_knots)
+    truth = synth.truth_theta(n_knots, wl.resonances, seed)
+    m = oracle_model(wl, knots=kn)
+    s12, s13, _ = OG.toy(m, truth, n, seed=seed, n_probe=100_000)
+    start = synth.perturb_theta(truth, n_knots, wl.n_res, seed + 7)
+    return kn, truth, start, s12, s13
+
+
+@pytest.fixture(scope="module")
+def norm():
+    wl = synth.C1
+    s12, s13 = synth.uniform_phase_space(wl.decay, 100_000, 503)
+    area = K.area(oracle_model(wl))
+    return s12, s13, np.full(len(s12), area / len(s12))
+
+
+@pytest.fixture(scope="module")
+def jobs():
+    return {"A": _toy(4000, 20, 11), "B": _toy(8000, 30, 12), "C": _toy(2500, 20, 13), "D": _toy(3000, 40, 14)}
+
+
+def _server(norm, precision="mixed", budget=0):
+    from paper_1703_03284_amd import FP64, MIXED, Server
+    s = Server(MIXED if precision == "mixed" else FP64, hbm_budget_bytes=budget)
+    s.set_norm(*norm)
+    return s
+
+
+def _submit(srv, job, **kw):
+    wl = synth.C1
+    kn, _, start, s12, s13 = job
+    return srv.submit(wl.decay, kn, wl.resonances, s12, s13, start, **kw)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_result_alone_equals_result_in_the_mix(norm, jobs, precision):
+    with _server(norm, precision) as s1:
+        a = s1.wait(_submit(s1, jobs["A"]))
+    with _server(norm, precision) as s2:
+        ids = [_submit(s2, jobs[k]) for k in ("B", "A", "C", "D")]
+        res = [s2.wait(i) for i in ids]
+        st = s2.stats()
+    a_mix = res[1]
+    assert a["status"] == 0 and a_mix["status"] == 0
+    assert np.array_equal(a["theta"], a_mix["theta"])
+    assert a["nll"] == a_mix["nll"] and a["n_eval"] == a_mix["n_eval"]
+    assert st["n_done"] == 4 and st["mean_batch"] > 1.0
+
+
+def test_serving_fit_agrees_with_single_context_fit(norm, jobs):
+    from paper_1703_03284_amd import FP64, context_for
+    wl = synth.C1
+    kn, _, start, s12, s13 = jobs["A"]
+    with _server(norm, "fp64") as srv:
+        r = srv.wait(_submit(srv, jobs["A"], tol_edm=1e-8))
+    ctx = context_for(wl.decay, kn, wl.resonances, FP64)
+    ctx.load_events(s12, s13)
+    ctx.load_norm(*norm)
+    ref = ctx.fit(start, fixed=synth.fixed_mask(20, wl.n_res), tol_edm=1e-8)
+    free = np.flatnonzero(synth.fixed_mask(20, wl.n_res) == 0)
+    d = r["theta"] - ref.theta
+    npair = 20 + wl.n_res
+    d[1:2 * npair:2] = np.angle(np.exp(1j * d[1:2 * npair:2]))
+    assert (np.abs(d[free]) / ref.sigma[free]).max() < 0.01
+
+
+def test_admission_under_a_small_budget(norm, jobs):
+    # room for the normalisation sets and about one job at a time
+    with _server(norm, "mixed", budget=48 << 20) as srv:
+        ids = [_submit(srv, jobs[k]) for k in ("A", "B", "C", "D")]
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert all(r["status"] == 0 for r in res)
+    assert st["n_done"] == 4
+
+
+def test_cancel_leaves_other_jobs_alone(norm, jobs):
+    with _server(norm, "mixed") as ref_srv:
+        ref = ref_srv.wait(_submit(ref_srv, jobs["C"]))
+    with _server(norm, "mixed") as srv:
+        a = _submit(srv, jobs["A"])
+        b = _submit(srv, jobs["B"])
+        c = _submit(srv, jobs["C"])
+        srv.cancel(b)
+        ra, rb, rc = srv.wait(a), srv.wait(b), srv.wait(c)
+    assert rb["status"] == -7
+    assert ra["status"] == 0 and rc["status"] == 0
+    assert np.array_equal(rc["theta"], ref["theta"])
+
+
+def test_invalid_submissions_are_rejected(norm, jobs):
+    from paper_1703_03284_amd import MipwaError
+    wl = synth.C1
+    kn, _, start, s12, s13 = jobs["A"]
+    with _server(norm, "mixed") as srv:
+        fx = synth.fixed_mask(20, wl.n_res, float_shapes=True)
+        with pytest.raises(MipwaError):
+            srv.submit(wl.decay, kn, wl.resonances, s12, s13, start, fixed=fx)
+        bad = start.copy()
+        bad[-1] = -1.0
+        with pytest.raises(MipwaError):
+            srv.submit(wl.decay, kn, wl.resonances, s12, s13, bad)
+        ok = srv.wait(_submit(srv, jobs["C"]))
+        assert ok["status"] == 0
