@@ -118,6 +118,85 @@ def cpu_baseline(wl, n_events, n_norm, sample=2_000_000, reps=3):
                       f"scaled x{scale:.0f} to the full workload; {t:.2f} s per sample evaluation"}
 
 
+def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
+    """Toy-fit serving: n_jobs fits (event counts log-uniform in [1e4, 5e6], knots in {20,30,40,50},
+    rho(770)+f2(1270), shapes fixed) against one shared 2M-point normalisation sample.  Run 1 submits
+    every job at t=0 (capacity); run 2 submits them at Poisson arrival times with rate
+    rate_factor x capacity and reports fits/s and p50/p99 time-to-fit."""
+    import synth
+    from paper_1703_03284_amd import FP64, Server, context_for
+    wl = synth.C1
+    d = wl.decay
+    specs = synth.serving_jobs(n_jobs)
+    n12, n13 = synth.uniform_phase_space(d, 2_000_000, synth.SERVE_NORM_SEED)
+    w = np.full(len(n12), synth.region_area_mc(d, 1 << 22, 5) / len(n12))
+    gens = {}
+    payload = []
+    t0 = time.time()
+    for i, (n, N, seed) in enumerate(specs):
+        if N not in gens:
+            gens[N] = context_for(d, synth.uniform_knots(d, N), wl.resonances, FP64)
+        truth = synth.truth_theta(N, wl.resonances, seed)
+        s12, s13, _ = gens[N].toy(truth, n, seed, n_probe=200_000)
+        payload.append((synth.uniform_knots(d, N), s12, s13, synth.perturb_theta(truth, N, wl.n_res, seed + 7)))
+    for g in gens.values():
+        g.close()
+    n_events = sum(len(p[1]) for p in payload)
+    log(f"[bench] serving: generated {n_events} toy events for {n_jobs} jobs in {time.time() - t0:.1f}s")
+
+    def run(arrivals):
+        srv = Server(precision)
+        srv.set_norm(n12, n13, w)
+        ids = []
+        start = time.perf_counter()
+        for i, (kn, s12, s13, th0) in enumerate(payload):
+            if arrivals is not None:
+                delay = arrivals[i] - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+            ids.append(srv.submit(d, kn, wl.resonances, s12, s13, th0, tol_edm=1e-4))
+        res = []
+        for k, j in enumerate(ids):
+            res.append(srv.wait(j))
+            if (k + 1) % log_every == 0:
+                log(f"[bench] serving: {k + 1}/{len(ids)} fits done")
+        wall = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        ok = sum(1 for r in res if r["status"] in (0, -6))
+        return wall, st, ok, res
+
+    wall0, st0, ok0, _ = run(None)
+    capacity = st0["fits_per_s"]
+    log(f"[bench] serving capacity run: {st0} wall {wall0:.1f}s")
+    rate = rate_factor * capacity
+    arrivals = synth.poisson_arrivals(n_jobs, rate, seed=502)
+    wall1, st1, ok1, res1 = run(arrivals)
+    log(f"[bench] serving Poisson run: {st1} wall {wall1:.1f}s")
+    return {"jobs": n_jobs, "events_total": int(n_events), "norm_points": len(n12),
+            "capacity_fits_per_s": capacity, "arrival_rate_per_s": rate,
+            "fits_per_s": st1["fits_per_s"], "p50_s": st1["p50_s"], "p99_s": st1["p99_s"],
+            "mean_batch": st1["mean_batch"], "steps": st1["steps"], "peak_bytes": st1["peak_bytes"],
+            "converged": ok1, "mean_evals_per_fit": float(np.mean([r.get("n_eval", 0) for r in res1])),
+            "precision": "mixed" if precision == 1 else "fp64"}
+
+
+def profile_pass(steps):
+    """A few headline evaluations plus a 1 GiB device copy of known size (counter calibration)."""
+    import torch
+    import synth
+    from paper_1703_03284_amd import MIXED
+    wl = synth.C3
+    table, events, norm = build_inputs(wl, wl.n_events, wl.n_norm)
+    r = time_gpu(wl, MIXED, table, events, norm, steps, 2)
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] profile pass: {r}; copy of {a.numel() * 4} bytes x3")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,11 +208,17 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=256)
+    ap.add_argument("--profile-pass", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the likelihood would shard "
               "by points with one small all-reduce per evaluation; see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+    if args.profile_pass:
+        profile_pass(args.steps)
+        return
     import synth
     from paper_1703_03284_amd import FP64, MIXED
     wl = synth.C3
@@ -150,7 +235,7 @@ def main():
         n_nm * stream_bytes_per_point(4, wl.n_res, "norm")
     achieved = bytes_launch / (mixed["stream_kernel_ms"] * 1e-3) / 1e9
     out = {
-        "metric": "NLL+grad evals/sec @10M events (mixed vs FP64 GPU)",
+        "metric": "NLL+grad evals/sec @10M events (mixed vs FP64 GPU); toy fits/sec + p50/p99",
         "value": mixed["value"],
         "unit": "evals/s",
         "n_gpus": 1,
@@ -176,6 +261,8 @@ def main():
                      "kernel": "k_eval<float,2,false>", "bytes_per_launch": bytes_launch,
                      "kernel_ms": mixed["stream_kernel_ms"]},
     }
+    if not args.no_serve:
+        out["serving"] = serving(args.serve_jobs, MIXED)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, n_ev, n_nm)
     print(json.dumps(out), flush=True)

@@ -5,7 +5,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmipwa.so")
+LIB_PATH = os.environ.get("MIPWA_LIB") or os.path.join(_HERE, "libmipwa.so")
 
 MIPWA_FP64, MIPWA_MIXED = 0, 1
 STATUS = {0: "MIPWA_OK", -1: "MIPWA_E_INVAL", -2: "MIPWA_E_NOMEM", -3: "MIPWA_E_HIP", -4: "MIPWA_E_STATE",

@@ -29,6 +29,10 @@ struct mipwa_ctx {
   mipwa::DevBuf d_blob;
   mipwa::HostBuf h_blob;
   size_t tab64_off = 0, upload_bytes = 0;
+  // small tables go in the kernel arguments instead of an upload
+  bool use_arg = false;
+  int arg_theta_off = 0;
+  mipwa::ArgTable h_args{};
 
   mipwa::DevBuf d_segs, d_block_seg, d_records, d_grec, d_fin, d_gcount, d_out, d_job;
   mipwa::HostBuf h_out;          // mapped, coherent: the finish writes the results here

@@ -8,9 +8,14 @@
 
 namespace mipwa {
 
-// Points per tile.  A tile holds points of a single spline cell (j12, j13), so inside a tile both
-// interval indices are wave-uniform.
-constexpr int kTile = 256;
+// Points per tile (a multiple of 64).  A tile holds points of a single spline cell (j12, j13), so
+// inside a tile both interval indices are wave-uniform; each lane streams kTile/64 points of a tile
+// with all their loads issued together.
+#ifndef MIPWA_TILE
+#define MIPWA_TILE 256
+#endif
+constexpr int kTile = MIPWA_TILE;
+static_assert(kTile % 64 == 0, "tiles hold whole wavefronts");
 constexpr int kMaxWaves = 16;
 constexpr int kMaxRes = 4;
 constexpr int kMaxKnots = 128;
@@ -73,14 +78,24 @@ struct Job {
   double c_eps;          // -2 sum ln eff over the events
   int G_d, G_n;
   int N, R, rs, otf;
+  int theta_off;         // byte offset of theta in the launch's ArgTable when tab64 == nullptr
+  int pad;
 };
 
-inline int n_groups(int n_blocks) { return (n_blocks + kGroup - 1) / kGroup; }
+__host__ __device__ inline int n_groups(int n_blocks) { return (n_blocks + kGroup - 1) / kGroup; }
+
+// Small per-evaluation tables travel in the launch's kernel arguments: [table in working precision |
+// theta (FP64) at theta_off bytes].  A segment with table == nullptr and a job with tab64 == nullptr
+// read them from here.
+constexpr int kArgBytes = 3840;
+struct ArgTable {
+  double w[kArgBytes / 8];
+};
 
 // Record layout (doubles): [8 * nint spline-polynomial partials (interval j, power m, re/im)]
 // [sum] [2R: sum g conj(R_r)] [OTF: 2R sum g conj(dR_r/dm), 2R sum g conj(dR_r/dGamma)].
-inline int record_size(int nint, int R, bool otf) { return 8 * nint + 1 + 2 * R + (otf ? 4 * R : 0); }
-inline int table_words(int nint, int R) { return 8 * nint + 2 * R + kResWords * R; }
+__host__ __device__ inline int record_size(int nint, int R, bool otf) { return 8 * nint + 1 + 2 * R + (otf ? 4 * R : 0); }
+__host__ __device__ inline int table_words(int nint, int R) { return 8 * nint + 2 * R + kResWords * R; }
 
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
 hipError_t launch_cache(bool fp64, int R, const Segment* h_seg, const void* table, const void* kin,
@@ -91,7 +106,8 @@ hipError_t launch_cache(bool fp64, int R, const Segment* h_seg, const void* tabl
 // dispatch at the kernel's start and end.
 hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* d_segs, const int2* d_block_map,
                        const Job* d_jobs, int n_blocks, int waves, int max_nint, const void* kin,
-                       hipStream_t stream, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                       const ArgTable* args, hipStream_t stream, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 hipError_t launch_integrals(bool fp64, int R, const Segment* h_seg, const void* w_override,
                             double* d_records, int n_blocks, double* d_out, hipStream_t stream);
 hipError_t launch_eff_lookup(const double* d_s12, const double* d_s13, long long n, const float* d_table,

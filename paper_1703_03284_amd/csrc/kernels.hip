@@ -141,13 +141,12 @@ __global__ __launch_bounds__(256) void k_cache(Segment sg, const Real* __restric
 // K2: fused forward + adjoint over the tiles of one segment, persistent waves.
 
 template <typename Real, int R, bool OTF, int KIND>
-__device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& kin, double* bins,
+__device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& kin, const Real* tab, double* bins,
                                             double* scal, int wave, int lane, int waves, int local_block) {
   using O = Ops<Real>;
   using V2 = typename O::V2;
   constexpr int R1 = R > 0 ? R : 1;
   constexpr int IT = kTile / 64;
-  const Real* __restrict__ tab = (const Real*)sg.table;
   const Real* __restrict__ cv = tab + 8 * sg.nint;
   const Real* __restrict__ res = cv + 2 * R;
   Real cre[R1], cim[R1];
@@ -383,14 +382,14 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
 //   spline-polynomial partials -> knot values z and second derivatives M -> z through M = K z,
 //   then the chain rule to (a_k, phi_k), (|c_r|, arg c_r), (m_r, Gamma_r).
 
-__device__ void finish_job(const Job& jb) {
+__device__ void finish_job(const Job& jb, const ArgTable& targ) {
   const int N = jb.N, nint = N - 1, R = jb.R;
   const double* fd = jb.fin;
   const double* fn = jb.fin + jb.rs;
   const int s0 = 8 * nint;
   const double I = fn[s0];
   const double scale = jb.n_ev / I;
-  const double* th = jb.tab64;
+  const double* th = jb.tab64 ? jb.tab64 : (const double*)((const char*)targ.w + jb.theta_off);
   const double* thc = jb.consts;         // Thomas factors c'_i of the interior system
   const double* thinv = thc + (N - 2);   // 1 / pivot_i
   const double* h = thinv + (N - 2);
@@ -497,7 +496,8 @@ __device__ void finish_job(const Job& jb) {
 
 template <typename Real, int R, bool OTF>
 __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, const int2* __restrict__ block_map,
-                                              const Job* __restrict__ jobs, Kin<Real> kin, int max_nint) {
+                                              const Job* __restrict__ jobs, Kin<Real> kin, int max_nint,
+                                              ArgTable targ) {
   extern __shared__ double lds[];
   __shared__ int s_last;
   const int waves = blockDim.x >> 6;
@@ -507,14 +507,24 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
   const Segment sg = segs[bm.x];
   const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
   const int stride = 8 * max_nint;
-  double* bins = lds;
-  double* scal = lds + waves * stride;
-  for (int i = threadIdx.x; i < waves * stride + waves * nsc; i += blockDim.x) lds[i] = 0.0;
+  // LDS: [evaluation table | wave-private interval histograms | wave scalars]
+  const int tw = (table_words(max_nint, R) * (int)sizeof(Real) + 7) / 8;
+  double* tab_lds = lds;
+  double* bins = lds + tw;
+  double* scal = bins + waves * stride;
+  {
+    const unsigned* src = sg.table ? (const unsigned*)sg.table : (const unsigned*)targ.w;
+    unsigned* dst = (unsigned*)tab_lds;
+    const int words = table_words(sg.nint, R) * (int)sizeof(Real) / 4;
+    for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  }
+  for (int i = threadIdx.x; i < waves * stride + waves * nsc; i += blockDim.x) bins[i] = 0.0;
   __syncthreads();
+  const Real* tab = (const Real*)tab_lds;
   if (sg.kind == 0)
-    run_segment<Real, R, OTF, 0>(sg, kin, bins + wave * stride, scal, wave, lane, waves, bm.y);
+    run_segment<Real, R, OTF, 0>(sg, kin, tab, bins + wave * stride, scal, wave, lane, waves, bm.y);
   else
-    run_segment<Real, R, OTF, 1>(sg, kin, bins + wave * stride, scal, wave, lane, waves, bm.y);
+    run_segment<Real, R, OTF, 1>(sg, kin, tab, bins + wave * stride, scal, wave, lane, waves, bm.y);
   __syncthreads();
   const int rs = sg.rs;
   double* rec = sg.records + (long long)bm.y * rs;
@@ -573,7 +583,7 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
   }
   __threadfence();
   __syncthreads();
-  finish_job(jb);
+  finish_job(jb, targ);
   if (threadIdx.x == 0) __hip_atomic_store(jp->jcount, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -834,10 +844,13 @@ hipError_t cache_impl(int R, const Segment* s, const void* table, const void* ki
 
 template <typename Real, bool OTF>
 hipError_t eval_impl2(int R, const Segment* segs, const int2* bs, const Job* jobs, int nb, int waves, int max_nint,
-                      const void* kin, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                      const void* kin, const ArgTable* targ, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   Kin<Real> k = *(const Kin<Real>*)kin;
   const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
-  const size_t lds = (size_t)waves * (8 * max_nint + nsc) * sizeof(double);
+  const int tw = (table_words(max_nint, R) * (int)sizeof(Real) + 7) / 8;
+  const size_t lds = ((size_t)tw + (size_t)waves * (8 * max_nint + nsc)) * sizeof(double);
+  static const ArgTable empty{};
+  const ArgTable* ta = targ ? targ : &empty;
   const dim3 grid(nb), block(64 * waves);
   const void* fn = nullptr;
   switch (R) {
@@ -848,7 +861,7 @@ hipError_t eval_impl2(int R, const Segment* segs, const int2* bs, const Job* job
     case 4: fn = (const void*)k_eval<Real, 4, OTF>; break;
     default: return hipErrorInvalidValue;
   }
-  void* args[] = {(void*)&segs, (void*)&bs, (void*)&jobs, (void*)&k, (void*)&max_nint};
+  void* args[] = {(void*)&segs, (void*)&bs, (void*)&jobs, (void*)&k, (void*)&max_nint, (void*)ta};
   // start/stop events (when given) are recorded by the dispatch itself
   return hipExtLaunchKernel(fn, grid, block, args, lds, st, e0, e1, 0);
 }
@@ -878,12 +891,13 @@ hipError_t launch_cache(bool fp64, int R, const Segment* s, const void* table, c
 }
 
 hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const int2* bs, const Job* jobs, int nb,
-                       int waves, int max_nint, const void* kin, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                       int waves, int max_nint, const void* kin, const ArgTable* targ, hipStream_t st, hipEvent_t e0,
+                       hipEvent_t e1) {
   (void)hipGetLastError();
-  if (fp64) return otf ? eval_impl2<double, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, st, e0, e1)
-                       : eval_impl2<double, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, st, e0, e1);
-  return otf ? eval_impl2<float, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, st, e0, e1)
-             : eval_impl2<float, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, st, e0, e1);
+  if (fp64) return otf ? eval_impl2<double, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1)
+                       : eval_impl2<double, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1);
+  return otf ? eval_impl2<float, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1)
+             : eval_impl2<float, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1);
 }
 
 hipError_t launch_integrals(bool fp64, int R, const Segment* s, const void* w, double* rec, int nb, double* out,

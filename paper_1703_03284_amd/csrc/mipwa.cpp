@@ -71,7 +71,7 @@ int mipwa_ctx::rebuild_launch() {
     sg[k].w = k ? ps[k]->w.p : nullptr;
     sg[k].cache = ps[k]->cache.p;
     sg[k].tiles = ps[k]->tiles.as<Tile>();
-    sg[k].table = d_blob.p;
+    sg[k].table = use_arg ? nullptr : d_blob.p;
     sg[k].records = d_records.as<double>() + (size_t)(k ? nb_d : 0) * rs;
     sg[k].n = ps[k]->n;
     sg[k].n_tiles = ps[k]->n_tiles;
@@ -90,8 +90,10 @@ int mipwa_ctx::rebuild_launch() {
   Job jb[2];
   std::memset(jb, 0, sizeof(jb));
   for (int k = 0; k < 2; ++k) {
-    jb[k].tab64 = d_blob.as<double>() + tab64_off / sizeof(double);
-    jb[k].consts = jb[k].tab64 + mh.P;
+    const double* t64 = d_blob.as<double>() + tab64_off / sizeof(double);
+    jb[k].tab64 = use_arg ? nullptr : t64;
+    jb[k].theta_off = arg_theta_off;
+    jb[k].consts = t64 + mh.P;
     jb[k].grec = d_grec.as<double>();
     jb[k].fin = d_fin.as<double>();
     jb[k].gcount = d_gcount.as<unsigned int>();
@@ -133,6 +135,11 @@ int mipwa_ctx::stage_params() {
     for (size_t i = 0; i < tab.size(); ++i) f[i] = (float)tab[i];
   }
   std::memcpy(hb + tab64_off, theta.data(), mh.P * sizeof(double));
+  if (use_arg) {
+    char* a = reinterpret_cast<char*>(h_args.w);
+    std::memcpy(a, hb, tab.size() * (fp64 ? 8 : 4));
+    std::memcpy(a + arg_theta_off, theta.data(), mh.P * sizeof(double));
+  }
   return MIPWA_OK;
 }
 
@@ -160,11 +167,14 @@ int mipwa_ctx::ensure_cache(hipStream_t st) {
 int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed) {
   mipwa_ctx* ctx = this;
   if (timed) HIPCHK(hipEventRecord(ev_t0, st), "event");
-  HIPCHK(hipMemcpyAsync(d_blob.p, h_blob.p, upload_bytes, hipMemcpyHostToDevice, st), "parameter upload");
-  if (!to_host) HIPCHK(hipEventRecord(ev_staged, st), "event");
+  if (!use_arg) {
+    HIPCHK(hipMemcpyAsync(d_blob.p, h_blob.p, upload_bytes, hipMemcpyHostToDevice, st), "parameter upload");
+    HIPCHK(hipEventRecord(ev_staged, st), "event");
+  }
+  // with use_arg the table and theta travel in the kernel arguments (copied at the launch)
   HIPCHK(launch_eval(fp64, mh.R, otf, d_segs.as<Segment>(), d_block_seg.as<int2>(), d_job.as<Job>() + (to_host ? 0 : 1),
-                     n_blocks, waves_eff, mh.N - 1, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32, st,
-                     timed ? ev_t1 : nullptr, timed ? ev_t2 : nullptr),
+                     n_blocks, waves_eff, mh.N - 1, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32,
+                     use_arg ? &h_args : nullptr, st, timed ? ev_t1 : nullptr, timed ? ev_t2 : nullptr),
          "likelihood kernel");
   if (timed) HIPCHK(hipEventRecord(ev_t3, st), "event");
   return MIPWA_OK;
@@ -259,6 +269,8 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
   const size_t tbytes = table_words(mh.N - 1, mh.R) * real;
   ctx->tab64_off = (tbytes + 255) / 256 * 256;
   ctx->upload_bytes = ctx->tab64_off + mh.P * sizeof(double);
+  ctx->arg_theta_off = (int)((tbytes + 7) / 8 * 8);
+  ctx->use_arg = ctx->arg_theta_off + mh.P * sizeof(double) <= (size_t)kArgBytes;
   const size_t blob = ctx->tab64_off + ((size_t)mh.P + 2 * (size_t)mh.N + mh.N) * sizeof(double);
   if (ctx->d_blob.alloc(blob) != hipSuccess || ctx->h_blob.alloc(ctx->upload_bytes) != hipSuccess ||
       ctx->d_out.alloc((1 + mh.P) * sizeof(double)) != hipSuccess ||

@@ -445,7 +445,7 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
     if (launch_eval(S->fp64, R, false, reinterpret_cast<const Segment*>(db + o_seg),
                     reinterpret_cast<const int2*>(db + o_map), reinterpret_cast<const Job*>(db + o_job),
                     (int)map.size(), kServeWaves, max_nint,
-                    S->fp64 ? (const void*)&mh0.kin64 : (const void*)&mh0.kin32, S->stream) != hipSuccess)
+                    S->fp64 ? (const void*)&mh0.kin64 : (const void*)&mh0.kin32, nullptr, S->stream) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batched likelihood kernel failed");
     if (hipStreamSynchronize(S->stream) != hipSuccess) return S->fail(MIPWA_E_HIP, "batch sync failed");
   }

@@ -290,7 +290,9 @@ C2 = Workload("dpipipi_1M_fp64", 2, "fp64", 1_000_000, 2_000_000, 40, (RHO770, F
 C3 = Workload("dpipipi_10M_mixed", 3, "mixed", 10_000_000, 10_000_000, 50, (RHO770, F2_1270), "hist")
 C4 = Workload("dpipipi_5M_shapes", 4, "fp64", 5_000_000, 5_000_000, 50, (RHO770, F2_1270, RHO1450), "flat",
               float_shapes=True)
-WORKLOADS = {w.index: w for w in (C1, C2, C3, C4)}
+# The decay studied in the paper (Sec. 4): D+ -> K- K+ K+, 40 knots, phi(1020) P-wave, 100k toy events.
+KKK = Workload("dkkk_100k", 6, "fp64", 100_000, 1_000_000, 40, (PHI1020,), "flat", decay=D_KKK)
+WORKLOADS = {w.index: w for w in (C1, C2, C3, C4, KKK)}
 
 # Serving workload: 256 toy-fit jobs, event counts log-uniform in [1e4, 5e6], knots in {20,30,40,50},
 # model as the small fit, shapes fixed, shared normalisation sample.

@@ -1,0 +1,128 @@
+"""Checks at the benchmark workloads' full sizes, in the launch configuration bench.py times.
+
+The oracle computes -2 ln L at 10M + 10M points and the gradient at 1M + 2M points; at 5M + 5M with
+masses and widths floated (where the oracle's per-point five-point differences would take minutes)
+the checks are properties that hold at any size: the FP64 adjoint against central differences of
+the library's FP64 -2 ln L, and the mixed-precision gradient against the FP64 one.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import kinematics as K
+from oracle import likelihood as L
+from tests.cases import make_problem, rel
+from tests.conftest import oracle_model
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _prec(name):
+    from paper_1703_03284_amd import FP64, MIXED
+    return {"fp64": FP64, "mixed": MIXED}[name]
+
+
+@pytest.fixture(scope="module")
+def headline():
+    wl = synth.C3
+    d = wl.decay
+    m = oracle_model(wl)
+    table = synth.efficiency_histogram(synth.PolyEfficiency.seeded(d, wl.seed("eff")))
+    ev = synth.uniform_phase_space(d, wl.n_events, 31)
+    s12, s13 = synth.uniform_phase_space(d, wl.n_norm, wl.seed("norm"))
+    w = np.full(len(s12), K.area(m) / len(s12))
+    e_ev = L.hist_lookup(table, d.smin, d.smax, *ev)
+    e_nm = L.hist_lookup(table, d.smin, d.smax, s12, s13)
+    th = wl.start()
+    v_o = L.nll(m, th, ev, (s12, s13, w * e_nm), float(np.sum(np.log(e_ev))))
+    return wl, table, ev, (s12, s13, w), th, v_o
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-6), ("fp64", 1e-10)])
+def test_headline_nll_full_size(headline, prec, tol):
+    from paper_1703_03284_amd import context_for
+    wl, table, ev, nm, th, v_o = headline
+    d = wl.decay
+    ctx = context_for(d, wl.knots(), wl.resonances, _prec(prec))
+    ctx.set_eff_table(table, d.smin, d.smax)
+    ctx.load_events(*ev)
+    ctx.load_norm(*nm)
+    v, g = ctx.eval(th)
+    assert rel(v, v_o) <= tol, (v, v_o)
+    ctx.close()
+
+
+def test_headline_mixed_gradient_vs_fp64_full_size(headline):
+    from paper_1703_03284_amd import context_for
+    wl, table, ev, nm, th, _ = headline
+    d = wl.decay
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ctx = context_for(d, wl.knots(), wl.resonances, _prec(prec))
+        ctx.set_eff_table(table, d.smin, d.smax)
+        ctx.load_events(*ev)
+        ctx.load_norm(*nm)
+        out[prec] = ctx.eval(th)
+        ctx.close()
+    g64, g32 = out["fp64"][1], out["mixed"][1]
+    assert np.abs(g32 - g64).max() <= 1e-4 * np.abs(g64).max()
+
+
+def test_fp64_gradient_full_size_1m():
+    wl = synth.C2
+    prob = make_problem(wl, wl.n_events, wl.n_norm, seed=2)
+    ctx = prob.context(_prec("fp64"))
+    v, g = ctx.eval()
+    v_o, g_o = prob.oracle()
+    assert rel(v, v_o) <= 1e-10
+    n_ck = 2 * wl.n_knots + 2 * wl.n_res
+    assert np.abs(g[:n_ck] - g_o[:n_ck]).max() <= 1e-8 * np.abs(g_o[:n_ck]).max()
+
+
+def test_shape_gradient_full_size_5m():
+    from paper_1703_03284_amd import context_for
+    wl = synth.C4
+    d = wl.decay
+    m = oracle_model(wl)
+    ev = synth.uniform_phase_space(d, wl.n_events, 41)
+    s12, s13 = synth.uniform_phase_space(d, wl.n_norm, wl.seed("norm"))
+    w = np.full(len(s12), K.area(m) / len(s12))
+    th = wl.start()
+    ctxs = {}
+    for prec in ("fp64", "mixed"):
+        c = context_for(d, wl.knots(), wl.resonances, _prec(prec))
+        c.load_events(*ev)
+        c.load_norm(s12, s13, w)
+        c.set_fixed(wl.fixed())
+        ctxs[prec] = c
+    v64, g64 = ctxs["fp64"].eval(th)
+    v32, g32 = ctxs["mixed"].eval(th)
+    assert rel(v32, v64) <= 1e-6
+    assert np.abs(g32 - g64).max() <= 1e-4 * np.abs(g64).max()
+    N, R = wl.n_knots, wl.n_res
+    for p in range(2 * N + 2 * R, 2 * N + 4 * R):
+        tp, tm = th.copy(), th.copy()
+        tp[p] += 1e-6
+        tm[p] -= 1e-6
+        fd = (ctxs["fp64"].eval(tp)[0] - ctxs["fp64"].eval(tm)[0]) / 2e-6
+        assert abs(fd - g64[p]) <= 1e-4 * abs(g64[p]) + 1e-6 * np.abs(g64).max(), (p, fd, g64[p])
+    for c in ctxs.values():
+        c.close()
+
+
+def test_torch_autograd_and_device_output():
+    import torch
+    from paper_1703_03284_amd.torch_nll import MipwaNLL, nll_on_device
+    prob = make_problem(synth.C1, 3000, 20000, seed=6)
+    ctx = prob.context(_prec("fp64"))
+    v, g = ctx.eval(prob.theta)
+    theta = torch.tensor(prob.theta, dtype=torch.float64, requires_grad=True)
+    out = MipwaNLL.apply(theta, ctx)
+    (2.5 * out).backward()
+    assert out.item() == v
+    np.testing.assert_array_equal(theta.grad.numpy(), 2.5 * g)
+    dev = nll_on_device(torch.tensor(prob.theta, dtype=torch.float64), ctx)
+    torch.cuda.synchronize()
+    host = dev.cpu().numpy()
+    assert host[0] == v
+    np.testing.assert_array_equal(host[1:], g)

@@ -49,6 +49,16 @@ def test_nll_and_gradient_match_oracle(prec, wl, n_ev, n_nm):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_kkk_narrow_phi(prec):
+    """The paper's decay (Sec. 4): D+ -> K- K+ K+ with 40 knots and the narrow phi(1020)."""
+    wl = synth.KKK
+    prob = make_problem(wl, 5000, 30000, seed=6)
+    ctx = prob.context(_prec(prec))
+    tol = (FP64_NLL, FP64_G) if prec == "fp64" else (MIX_NLL, MIX_G)
+    _check(prob, ctx, *tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_large_cells_full_tiles_and_ragged_tails(prec):
     """Five knots: cells hold thousands of points, so tiles are full with one ragged tail per cell."""
     wl = synth.C2
