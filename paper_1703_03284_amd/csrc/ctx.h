@@ -34,12 +34,12 @@ struct mipwa_ctx {
   int arg_theta_off = 0;
   mipwa::ArgTable h_args{};
 
-  mipwa::DevBuf d_segs, d_block_seg, d_records, d_grec, d_fin, d_gcount, d_out, d_job;
+  mipwa::DevBuf d_segs, d_block_seg, d_records, d_grec, d_fin, d_tasks, d_out, d_job, d_res64;
   mipwa::HostBuf h_out;          // mapped, coherent: the finish writes the results here
   double* h_out_dev = nullptr;   // device view of h_out
   mipwa::Segment h_segs[2];
   int blocks_cfg = 512, waves_cfg = 0, waves_eff = 8;
-  int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0;
+  int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0, n_tasks = 0;
   bool launch_dirty = true;
 
   hipEvent_t ev_staged = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;

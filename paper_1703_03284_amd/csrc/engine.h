@@ -39,16 +39,16 @@ struct Kin {
   Real rD2;             // D barrier radius squared
 };
 
-// Blocks of one segment are reduced in groups of kGroup consecutive blocks: the last block of a
-// group to finish sums the group's records, the last group of a job sums the group records and runs
-// the FP64 finish.  Completion is detected with atomic counters only (no block waits for another).
+// Blocks of one segment are reduced in groups of kGroup consecutive blocks (k_group_sum), then the
+// group records of a job are summed and the FP64 finish runs (k_job_finish).  Each stage is its own
+// kernel, so no block ever reads another block's output within a launch.
 constexpr int kGroup = 32;
 
 // One stream of points (data events or normalisation points of one job) and where its per-block
 // partial records go.  Lives in device memory; read with uniform (scalar) loads.
 struct Segment {
   const void* tt;     // Real2[n]: (t12, t13), local spline coordinates of the two h+h- invariants
-  const void* ss;     // Real2[n]: (s12, s13), canonical order s12 <= s13
+  const void* ss;     // double2[n]: (s12, s13), canonical order s12 <= s13 (FP64 in both precisions)
   const void* w;      // Real[n]: weight x efficiency (normalisation points), nullptr for data
   const void* cache;  // Real2[R][n]: symmetrised resonance amplitudes R_r at each point
   const Tile* tiles;
@@ -72,8 +72,6 @@ struct Job {
   double* out;           // 1 + P results: -2 ln L, gradient (device or mapped host memory)
   double* grec;          // (G_d + G_n) x rs group records
   double* fin;           // 2 x rs: reduced data record, reduced normalisation record
-  unsigned int* gcount;  // G_d + G_n group counters, zero between evaluations
-  unsigned int* jcount;  // job counter, zero between evaluations
   double n_ev;
   double c_eps;          // -2 sum ln eff over the events
   int G_d, G_n;
@@ -98,16 +96,21 @@ __host__ __device__ inline int record_size(int nint, int R, bool otf) { return 8
 __host__ __device__ inline int table_words(int nint, int R) { return 8 * nint + 2 * R + kResWords * R; }
 
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
-hipError_t launch_cache(bool fp64, int R, const Segment* h_seg, const void* table, const void* kin,
+// resonance cache of a segment, computed in FP64 from res64 (device, kResWords x R FP64 constants) and
+// stored in working precision
+hipError_t launch_cache(bool fp64, int R, const Segment* h_seg, const double* res64, const Kin<double>& kin64,
                         hipStream_t stream);
 // e0/e1 (nullable): HIP events recorded by the dispatch at the kernel's start and end
-// d_block_map[b] = (segment, block index within that segment) for every block b of the grid; the
-// kernel also reduces and finishes every job of d_jobs.  e0/e1 (nullable): HIP events recorded by the
-// dispatch at the kernel's start and end.
+// d_block_map[b] = (segment, block index within that segment) for every block b of the grid; each
+// block writes its FP64 record.  e0/e1 (nullable): HIP events recorded by the dispatch at the kernel's
+// start and end.
 hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* d_segs, const int2* d_block_map,
                        const Job* d_jobs, int n_blocks, int waves, int max_nint, const void* kin,
                        const ArgTable* args, hipStream_t stream, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
+// group sums (one block per task (segment, group)) then one finishing block per job
+hipError_t launch_reduce(const Segment* d_segs, const Job* d_jobs, const int2* d_tasks, int n_tasks, int n_jobs,
+                         const ArgTable* args, hipStream_t stream);
 hipError_t launch_integrals(bool fp64, int R, const Segment* h_seg, const void* w_override,
                             double* d_records, int n_blocks, double* d_out, hipStream_t stream);
 hipError_t launch_eff_lookup(const double* d_s12, const double* d_s13, long long n, const float* d_table,

@@ -203,6 +203,14 @@ void ModelHost::res_table(const double* theta, double* out) const {
   }
 }
 
+int ModelHost::upload_res64(const double* theta, DevBuf& d) const {
+  std::vector<double> r((size_t)kResWords * std::max(R, 1), 0.0);
+  res_table(theta, r.data());
+  if (d.alloc(r.size() * sizeof(double)) != hipSuccess) return MIPWA_E_NOMEM;
+  if (hipMemcpy(d.p, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return MIPWA_E_HIP;
+  return MIPWA_OK;
+}
+
 int ModelHost::interval(double s) const {
   // number of knots <= s, minus one, clamped to [0, N-2]
   const int c = (int)(std::upper_bound(knots.begin(), knots.end(), s) - knots.begin());
@@ -249,21 +257,22 @@ int upload_sorted(const ModelHost& mh, const std::vector<double>& a, const std::
                   const std::vector<double>* wsorted, const std::vector<double>* wplain, PointSet& ps,
                   std::string& err) {
   const long long n = (long long)order.size();
-  std::vector<Real> tt(2 * n), ss(2 * n);
+  std::vector<Real> tt(2 * n);
+  std::vector<double> ss(2 * n);
   for (long long i = 0; i < n; ++i) {
     const long long o = order[i];
     tt[2 * i] = Real((a[o] - mh.knots[ja[o]]) / mh.h[ja[o]]);
     tt[2 * i + 1] = Real((b[o] - mh.knots[jb[o]]) / mh.h[jb[o]]);
-    ss[2 * i] = Real(a[o]);
-    ss[2 * i + 1] = Real(b[o]);
+    ss[2 * i] = a[o];
+    ss[2 * i + 1] = b[o];
   }
-  if (ps.tt.alloc(tt.size() * sizeof(Real)) != hipSuccess || ps.ss.alloc(ss.size() * sizeof(Real)) != hipSuccess ||
+  if (ps.tt.alloc(tt.size() * sizeof(Real)) != hipSuccess || ps.ss.alloc(ss.size() * sizeof(double)) != hipSuccess ||
       ps.cache.alloc((size_t)std::max(mh.R, 1) * 2 * n * sizeof(Real)) != hipSuccess) {
     err = "device allocation failed for points";
     return MIPWA_E_NOMEM;
   }
   if (hipMemcpy(ps.tt.p, tt.data(), tt.size() * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(ps.ss.p, ss.data(), ss.size() * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(ps.ss.p, ss.data(), ss.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     err = "copy of points to the device failed";
     return MIPWA_E_HIP;
   }

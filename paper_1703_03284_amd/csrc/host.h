@@ -95,6 +95,8 @@ struct ModelHost {
   void poly_table(const double* theta, double* out) const;
   // per-resonance constants (kResWords doubles each) at the given masses/widths in theta
   void res_table(const double* theta, double* out) const;
+  // FP64 resonance constants at theta into a device buffer (synchronous)
+  int upload_res64(const double* theta, DevBuf& d) const;
   int interval(double s) const;
   bool inside(double s12, double s13, double tol) const;
   int check_theta(const double* theta, std::string& err) const;

@@ -118,22 +118,24 @@ __device__ __forceinline__ void bw_pairing(const Kin<Real>& k, const Real* __res
 // ---------------------------------------------------------------------------------------------
 // K1: symmetrised resonance amplitudes R_r = BW_r(s12,s13) + BW_r(s13,s12) at every point.
 
+// Computed in FP64 from the FP64 coordinates in both precisions and rounded once when stored (the cache
+// is rebuilt only when a mass or width changes, so its cost does not enter an evaluation; FP64 keeps
+// m_r^2 - x accurate next to narrow poles).
 template <typename Real, int R>
-__global__ __launch_bounds__(256) void k_cache(Segment sg, const Real* __restrict__ table, Kin<Real> kin) {
+__global__ __launch_bounds__(256) void k_cache(Segment sg, const double* __restrict__ res, Kin<double> kin) {
   using V2 = typename Ops<Real>::V2;
   constexpr int R1 = R > 0 ? R : 1;
-  const Real* res = table + 8 * sg.nint + 2 * R;
-  const V2* __restrict__ ss = (const V2*)sg.ss;
+  const double2* __restrict__ ss = (const double2*)sg.ss;
   V2* __restrict__ cache = (V2*)sg.cache;
   const long long n = sg.n;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (long long)gridDim.x * blockDim.x) {
-    const V2 s = ss[p];
-    Real br[R1] = {}, bi[R1] = {};
-    bw_pairing<Real, R, false>(kin, res, s.x, s.y, br, bi, nullptr, nullptr, nullptr, nullptr);
-    bw_pairing<Real, R, false>(kin, res, s.y, s.x, br, bi, nullptr, nullptr, nullptr, nullptr);
+    const double2 s = ss[p];
+    double br[R1] = {}, bi[R1] = {};
+    bw_pairing<double, R, false>(kin, res, s.x, s.y, br, bi, nullptr, nullptr, nullptr, nullptr);
+    bw_pairing<double, R, false>(kin, res, s.y, s.x, br, bi, nullptr, nullptr, nullptr, nullptr);
 #pragma unroll
-    for (int r = 0; r < R; ++r) cache[(long long)r * n + p] = V2{br[r], bi[r]};
+    for (int r = 0; r < R; ++r) cache[(long long)r * n + p] = V2{(Real)br[r], (Real)bi[r]};
   }
 }
 
@@ -156,7 +158,7 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     cim[r] = cv[2 * r + 1];
   }
   const V2* __restrict__ tt = (const V2*)sg.tt;
-  const V2* __restrict__ ss = (const V2*)sg.ss;
+  const double2* __restrict__ ss = (const double2*)sg.ss;
   const Real* __restrict__ ww = (const Real*)sg.w;
   const V2* __restrict__ cache = (const V2*)sg.cache;
   const long long n = sg.n;
@@ -230,7 +232,7 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     for (int ib = 0; ib < IT; ib += IB) {
       V2 tv[IB];
       V2 rv[IB][R1];
-      V2 sv[IB];
+      double2 sv[IB];
       Real wv[IB];
       bool valid[IB];
 #pragma unroll
@@ -258,8 +260,9 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
         if constexpr (OTF) {
 #pragma unroll
           for (int r = 0; r < R1; ++r) rr[r] = ri[r] = dmr[r] = dmi[r] = dgr[r] = dgi[r] = Real(0);
-          bw_pairing<Real, R, true>(kin, res, sv[k].x, sv[k].y, rr, ri, dmr, dmi, dgr, dgi);
-          bw_pairing<Real, R, true>(kin, res, sv[k].y, sv[k].x, rr, ri, dmr, dmi, dgr, dgi);
+          const Real x12s = (Real)sv[k].x, x13s = (Real)sv[k].y;
+          bw_pairing<Real, R, true>(kin, res, x12s, x13s, rr, ri, dmr, dmi, dgr, dgi);
+          bw_pairing<Real, R, true>(kin, res, x13s, x12s, rr, ri, dmr, dmi, dgr, dgi);
         } else {
 #pragma unroll
           for (int r = 0; r < R; ++r) {
@@ -499,7 +502,6 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
                                               const Job* __restrict__ jobs, Kin<Real> kin, int max_nint,
                                               ArgTable targ) {
   extern __shared__ double lds[];
-  __shared__ int s_last;
   const int waves = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -539,41 +541,38 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
     rec[f] = s;
   }
 
-  // reduction tail: last block of the group, then last group of the job
-  const Job* jp = jobs + sg.job;
-  const int g = bm.y / kGroup;
+}
+
+// ---------------------------------------------------------------------------------------------
+// K3: group sums.  Task t = (segment, group): the records of blocks [32 g, 32 g + 32) of the segment,
+// summed in block order into the job's group record.  No cross-block communication inside a kernel:
+// the kernel boundary after the streaming kernel makes its records visible.
+
+__global__ __launch_bounds__(256) void k_group_sum(const Segment* __restrict__ segs, const Job* __restrict__ jobs,
+                                                   const int2* __restrict__ tasks) {
+  const int2 tk = tasks[blockIdx.x];
+  const Segment& sg = segs[tk.x];
+  const Job& jb = jobs[sg.job];
+  const int g = tk.y;
+  const int rs = sg.rs;
   const int gsz = min(kGroup, sg.n_blocks - g * kGroup);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev =
-        __hip_atomic_fetch_add(jp->gcount + sg.g0 + g, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = prev == (unsigned)(gsz - 1);
+  const double* rb = sg.records + (long long)g * kGroup * rs;
+  double* go = jb.grec + (long long)(sg.g0 + g) * rs;
+  for (int f = threadIdx.x; f < rs; f += blockDim.x) {
+    double v[kGroup];
+#pragma unroll
+    for (int b = 0; b < kGroup; ++b) v[b] = b < gsz ? rb[(long long)b * rs + f] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < kGroup; ++b) s += v[b];
+    go[f] = s;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  {
-    const double* rb = sg.records + (long long)g * kGroup * rs;
-    double* go = jp->grec + (long long)(sg.g0 + g) * rs;
-    for (int f = threadIdx.x; f < rs; f += blockDim.x) {
-      double s = 0.0;
-#pragma unroll 8
-      for (int b = 0; b < gsz; ++b) s += rb[(long long)b * rs + f];
-      go[f] = s;
-    }
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(jp->gcount + sg.g0 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned prev = __hip_atomic_fetch_add(jp->jcount, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = prev == (unsigned)(jp->G_d + jp->G_n - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const Job jb = *jp;
+}
+
+// K4: one block per job: sum the group records in order and run the FP64 finish.
+__global__ __launch_bounds__(256) void k_job_finish(const Job* __restrict__ jobs, ArgTable targ) {
+  const Job jb = jobs[blockIdx.x];
+  const int rs = jb.rs;
   for (int f = threadIdx.x; f < rs; f += blockDim.x) {
     double d = 0.0, q = 0.0;
     for (int k = 0; k < jb.G_d; ++k) d += jb.grec[(long long)k * rs + f];
@@ -581,10 +580,8 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
     jb.fin[f] = d;
     jb.fin[rs + f] = q;
   }
-  __threadfence();
   __syncthreads();
   finish_job(jb, targ);
-  if (threadIdx.x == 0) __hip_atomic_store(jp->jcount, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -826,17 +823,15 @@ __global__ __launch_bounds__(kGenBlock) void k_scatter(const unsigned char* __re
 
 namespace {
 template <typename Real>
-hipError_t cache_impl(int R, const Segment* s, const void* table, const void* kin, hipStream_t st) {
-  const Kin<Real>& k = *(const Kin<Real>*)kin;
-  const Real* tab = (const Real*)table;
+hipError_t cache_impl(int R, const Segment* s, const double* res, const Kin<double>& k, hipStream_t st) {
   const long long want = (s->n + 255) / 256;
   const int grid = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
   switch (R) {
     case 0: return hipSuccess;
-    case 1: k_cache<Real, 1><<<grid, 256, 0, st>>>(*s, tab, k); break;
-    case 2: k_cache<Real, 2><<<grid, 256, 0, st>>>(*s, tab, k); break;
-    case 3: k_cache<Real, 3><<<grid, 256, 0, st>>>(*s, tab, k); break;
-    case 4: k_cache<Real, 4><<<grid, 256, 0, st>>>(*s, tab, k); break;
+    case 1: k_cache<Real, 1><<<grid, 256, 0, st>>>(*s, res, k); break;
+    case 2: k_cache<Real, 2><<<grid, 256, 0, st>>>(*s, res, k); break;
+    case 3: k_cache<Real, 3><<<grid, 256, 0, st>>>(*s, res, k); break;
+    case 4: k_cache<Real, 4><<<grid, 256, 0, st>>>(*s, res, k); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -885,9 +880,10 @@ hipError_t integrals_impl(int R, const Segment* s, const void* w, double* rec, i
 }
 }  // namespace
 
-hipError_t launch_cache(bool fp64, int R, const Segment* s, const void* table, const void* kin, hipStream_t st) {
+hipError_t launch_cache(bool fp64, int R, const Segment* s, const double* res64, const Kin<double>& kin64,
+                        hipStream_t st) {
   (void)hipGetLastError();
-  return fp64 ? cache_impl<double>(R, s, table, kin, st) : cache_impl<float>(R, s, table, kin, st);
+  return fp64 ? cache_impl<double>(R, s, res64, kin64, st) : cache_impl<float>(R, s, res64, kin64, st);
 }
 
 hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const int2* bs, const Job* jobs, int nb,
@@ -898,6 +894,17 @@ hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const in
                        : eval_impl2<double, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1);
   return otf ? eval_impl2<float, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1)
              : eval_impl2<float, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1);
+}
+
+hipError_t launch_reduce(const Segment* segs, const Job* jobs, const int2* tasks, int n_tasks, int n_jobs,
+                         const ArgTable* targ, hipStream_t st) {
+  (void)hipGetLastError();
+  static const ArgTable empty{};
+  k_group_sum<<<n_tasks, 256, 0, st>>>(segs, jobs, tasks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_job_finish<<<n_jobs, 256, 0, st>>>(jobs, targ ? *targ : empty);
+  return hipGetLastError();
 }
 
 hipError_t launch_integrals(bool fp64, int R, const Segment* s, const void* w, double* rec, int nb, double* out,

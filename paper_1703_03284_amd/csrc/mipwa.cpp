@@ -56,8 +56,12 @@ int mipwa_ctx::rebuild_launch() {
   HIPCHK(d_records.alloc((size_t)B * rs * sizeof(double)), "records allocation");
   HIPCHK(d_grec.alloc((size_t)(G_d + G_n) * rs * sizeof(double)), "group records allocation");
   HIPCHK(d_fin.alloc(2 * (size_t)rs * sizeof(double)), "finish scratch allocation");
-  HIPCHK(d_gcount.alloc((size_t)(G_d + G_n + 1) * sizeof(unsigned)), "counter allocation");
-  HIPCHK(hipMemset(d_gcount.p, 0, (size_t)(G_d + G_n + 1) * sizeof(unsigned)), "counter reset");
+  std::vector<int2> tasks;
+  for (int g = 0; g < G_d; ++g) tasks.push_back(int2{0, g});
+  for (int g = 0; g < G_n; ++g) tasks.push_back(int2{1, g});
+  n_tasks = (int)tasks.size();
+  HIPCHK(d_tasks.alloc(tasks.size() * sizeof(int2)), "task allocation");
+  HIPCHK(hipMemcpy(d_tasks.p, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice), "task upload");
   std::vector<int2> bs(B);
   for (int b = 0; b < B; ++b) bs[b] = b < nb_d ? int2{0, b} : int2{1, b - nb_d};
   HIPCHK(d_block_seg.alloc(B * sizeof(int2)), "block map allocation");
@@ -96,8 +100,6 @@ int mipwa_ctx::rebuild_launch() {
     jb[k].consts = t64 + mh.P;
     jb[k].grec = d_grec.as<double>();
     jb[k].fin = d_fin.as<double>();
-    jb[k].gcount = d_gcount.as<unsigned int>();
-    jb[k].jcount = d_gcount.as<unsigned int>() + G_d + G_n;
     jb[k].n_ev = (double)ev.n;
     jb[k].c_eps = ev.c_eps;
     jb[k].G_d = G_d;
@@ -153,11 +155,12 @@ bool mipwa_ctx::shapes_changed() const {
 int mipwa_ctx::ensure_cache(hipStream_t st) {
   mipwa_ctx* ctx = this;
   if (!shapes_changed()) return MIPWA_OK;
+  HIPCHK(hipStreamSynchronize(st), "stream sync");
+  if (int rc = mh.upload_res64(theta.data(), d_res64)) return fail(rc, "resonance constants upload failed");
   PointSet* ps[2] = {&ev, &nm};
   for (int k = 0; k < 2; ++k) {
     if (!ps[k]->loaded) continue;
-    HIPCHK(launch_cache(fp64, mh.R, &h_segs[k], d_blob.p, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32, st),
-           "resonance cache kernel");
+    HIPCHK(launch_cache(fp64, mh.R, &h_segs[k], d_res64.as<double>(), mh.kin64, st), "resonance cache kernel");
   }
   cache_shape.assign(theta.begin() + 2 * mh.N + 2 * mh.R, theta.end());
   cache_valid = ev.loaded && nm.loaded;
@@ -176,12 +179,14 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed) {
                      n_blocks, waves_eff, mh.N - 1, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32,
                      use_arg ? &h_args : nullptr, st, timed ? ev_t1 : nullptr, timed ? ev_t2 : nullptr),
          "likelihood kernel");
+  HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), d_tasks.as<int2>(), n_tasks, 1,
+                       use_arg ? &h_args : nullptr, st),
+         "reduction kernels");
   if (timed) HIPCHK(hipEventRecord(ev_t3, st), "event");
   return MIPWA_OK;
 }
 
 int mipwa_ctx::prepare_eval(hipStream_t st) {
-  mipwa_ctx* ctx = this;
   if (!ev.loaded || !nm.loaded) return fail(MIPWA_E_STATE, "load events and normalisation points first");
   if (!have_theta) return fail(MIPWA_E_STATE, "set parameters first");
   if (launch_dirty) {
@@ -191,8 +196,6 @@ int mipwa_ctx::prepare_eval(hipStream_t st) {
   int rc = stage_params();
   if (rc) return rc;
   if (!otf && shapes_changed()) {
-    // the resonance cache needs this evaluation's shape constants on the device first
-    HIPCHK(hipMemcpyAsync(d_blob.p, h_blob.p, upload_bytes, hipMemcpyHostToDevice, st), "parameter upload");
     rc = ensure_cache(st);
     if (rc) return rc;
   }
@@ -470,9 +473,8 @@ int mipwa_integrals(mipwa_ctx* ctx, int with_eff, double* Ijk) {
   sg.n_tiles = ctx->nm.n_tiles;
   sg.kind = 1;
   sg.nint = ctx->mh.N - 1;
-  HIPCHK(launch_cache(ctx->fp64, ctx->mh.R, &sg, ctx->d_blob.p,
-                      ctx->fp64 ? (const void*)&ctx->mh.kin64 : (const void*)&ctx->mh.kin32, st),
-         "resonance cache kernel");
+  if (int rc2 = ctx->mh.upload_res64(ctx->theta.data(), ctx->d_res64)) return ctx->fail(rc2, "resonance constants upload");
+  HIPCHK(launch_cache(ctx->fp64, ctx->mh.R, &sg, ctx->d_res64.as<double>(), ctx->mh.kin64, st), "resonance cache kernel");
   ctx->cache_valid = false;  // the event cache was not rebuilt for these shapes
   const int K = ctx->mh.R + 1;
   const int nb = std::max(1, std::min(1024, (ctx->nm.n_tiles + 3) / 4));

@@ -67,7 +67,7 @@ struct SJob {
   PointSet ev;
   NormSet* norm = nullptr;
   int nb_d = 0, G_d = 0, G_n = 0, rs = 0;
-  DevBuf d_rec, d_grec, d_fin, d_cnt, d_consts, d_tab;
+  DevBuf d_rec, d_grec, d_fin, d_consts, d_tab;
   size_t bytes = 0;
   JobState state = QUEUED;
   int status = MIPWA_OK;
@@ -206,12 +206,10 @@ NormSet* get_norm(mipwa_server* S, const ModelHost& mh, const std::vector<double
   rc = load_points(mh, S->fp64, 1, S->n12.data(), S->n13.data(), S->nw.data(), nullptr, (long long)S->n12.size(),
                    none, st, ns->ps, err);
   if (rc) return nullptr;
-  std::vector<char> tab;
-  stage(mh, S->fp64, theta.data(), tab);
-  DevBuf dt;
+  DevBuf dr;
   Segment sg = cache_segment(ns->ps, mh.N - 1);
-  if (dt.alloc(tab.size()) != hipSuccess || hipMemcpy(dt.p, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      launch_cache(S->fp64, mh.R, &sg, dt.p, S->fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32, st) != hipSuccess ||
+  if (mh.upload_res64(theta.data(), dr) != MIPWA_OK ||
+      launch_cache(S->fp64, mh.R, &sg, dr.as<double>(), mh.kin64, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     err = "normalisation cache build failed";
     rc = MIPWA_E_HIP;
@@ -219,7 +217,7 @@ NormSet* get_norm(mipwa_server* S, const ModelHost& mh, const std::vector<double
   }
   const size_t real = S->fp64 ? 8 : 4;
   ns->nb = seg_blocks(ns->ps.n_tiles);
-  ns->bytes = (size_t)ns->ps.n * (6 + 2 * mh.R) * real + (size_t)ns->ps.n_tiles * sizeof(Tile);
+  ns->bytes = (size_t)ns->ps.n * ((4 + 2 * mh.R) * real + 16) + (size_t)ns->ps.n_tiles * sizeof(Tile);
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->used += ns->bytes;
@@ -243,7 +241,6 @@ void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
   J->d_rec.release();
   J->d_grec.release();
   J->d_fin.release();
-  J->d_cnt.release();
   J->d_consts.release();
   S->used -= J->bytes;
   S->running -= 1;
@@ -269,8 +266,6 @@ static void serve_worker(mipwa_server* S, SJob* J) {
   if (!rc) ns = get_norm(S, J->mh, J->theta0, st, err, rc);
   if (!rc) {
     // resonance cache of the events at the job's (fixed) shapes; per-job reduction scratch
-    std::vector<char> tab;
-    stage(J->mh, S->fp64, J->theta0.data(), tab);
     Segment sg = cache_segment(J->ev, J->mh.N - 1);
     J->norm = ns;
     J->nb_d = seg_blocks(J->ev.n_tiles);
@@ -284,17 +279,14 @@ static void serve_worker(mipwa_server* S, SJob* J) {
       cst[ni + i] = 1.0 / J->mh.th_d[i];
     }
     std::copy(J->mh.h.begin(), J->mh.h.end(), cst.begin() + 2 * ni);
-    const size_t cnt = (size_t)(J->G_d + J->G_n + 1) * sizeof(unsigned);
-    if (J->d_tab.alloc(tab.size()) || J->d_rec.alloc((size_t)(J->nb_d + ns->nb) * J->rs * 8) ||
+    if (J->mh.upload_res64(J->theta0.data(), J->d_tab) != MIPWA_OK ||
+        J->d_rec.alloc((size_t)(J->nb_d + ns->nb) * J->rs * 8) ||
         J->d_grec.alloc((size_t)(J->G_d + J->G_n) * J->rs * 8) || J->d_fin.alloc(2 * (size_t)J->rs * 8) ||
-        J->d_cnt.alloc(cnt) || J->d_consts.alloc(cst.size() * 8)) {
+        J->d_consts.alloc(cst.size() * 8)) {
       rc = MIPWA_E_NOMEM;
       err = "device allocation for a job failed";
-    } else if (hipMemcpy(J->d_tab.p, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
-               hipMemcpy(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-               hipMemset(J->d_cnt.p, 0, cnt) != hipSuccess ||
-               launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.p,
-                            S->fp64 ? (const void*)&J->mh.kin64 : (const void*)&J->mh.kin32, st) != hipSuccess ||
+    } else if (hipMemcpy(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+               launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
                hipStreamSynchronize(st) != hipSuccess) {
       rc = MIPWA_E_HIP;
       err = "loading a job failed";
@@ -378,7 +370,13 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
       off = (off + bytes + 255) / 256 * 256;
       return o;
     };
+    std::vector<int2> tasks;
+    for (int j = 0; j < nj; ++j) {
+      for (int g = 0; g < js[j]->G_d; ++g) tasks.push_back(int2{2 * j, g});
+      for (int g = 0; g < js[j]->G_n; ++g) tasks.push_back(int2{2 * j + 1, g});
+    }
     const size_t o_map = take(map.size() * sizeof(int2));
+    const size_t o_task = take(tasks.size() * sizeof(int2));
     const size_t o_seg = take((size_t)2 * nj * sizeof(Segment));
     const size_t o_job = take((size_t)nj * sizeof(Job));
     std::vector<size_t> o_tab(nj), o_th(nj);
@@ -395,6 +393,7 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
     char* hb = S->h_batch.as<char>();
     char* db = S->d_batch.as<char>();
     std::memcpy(hb + o_map, map.data(), map.size() * sizeof(int2));
+    std::memcpy(hb + o_task, tasks.data(), tasks.size() * sizeof(int2));
     Segment* sg = reinterpret_cast<Segment*>(hb + o_seg);
     Job* jb = reinterpret_cast<Job*>(hb + o_job);
     std::memset(sg, 0, (size_t)2 * nj * sizeof(Segment));
@@ -428,8 +427,6 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
       q.out = S->h_res_dev + res_of[J];
       q.grec = J->d_grec.as<double>();
       q.fin = J->d_fin.as<double>();
-      q.gcount = J->d_cnt.as<unsigned int>();
-      q.jcount = J->d_cnt.as<unsigned int>() + J->G_d + J->G_n;
       q.n_ev = (double)J->ev.n;
       q.c_eps = 0.0;
       q.G_d = J->G_d;
@@ -447,6 +444,9 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
                     (int)map.size(), kServeWaves, max_nint,
                     S->fp64 ? (const void*)&mh0.kin64 : (const void*)&mh0.kin32, nullptr, S->stream) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batched likelihood kernel failed");
+    if (launch_reduce(reinterpret_cast<const Segment*>(db + o_seg), reinterpret_cast<const Job*>(db + o_job),
+                      reinterpret_cast<const int2*>(db + o_task), (int)tasks.size(), nj, nullptr, S->stream) != hipSuccess)
+      return S->fail(MIPWA_E_HIP, "batched reduction kernels failed");
     if (hipStreamSynchronize(S->stream) != hipSuccess) return S->fail(MIPWA_E_HIP, "batch sync failed");
   }
   const double* res = S->h_res.as<double>();
@@ -583,7 +583,7 @@ int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double*
   J->max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 1000;
   J->hessian = opts ? opts->hessian != 0 : false;
   const size_t real = S->fp64 ? 8 : 4;
-  J->bytes = (size_t)n * (4 + 2 * R) * real + (size_t)(n / kTile + 1) * 2 * sizeof(Tile) +
+  J->bytes = (size_t)n * ((2 + 2 * R) * real + 16) + (size_t)(n / kTile + 1) * 2 * sizeof(Tile) +
              (size_t)(2 * kMaxSegBlocks + 32) * record_size(N - 1, R, false) * 8;
   if (J->bytes > S->budget) return S->fail(MIPWA_E_NOMEM, "the job alone exceeds the HBM budget");
   std::lock_guard<std::mutex> lk(S->mu);
