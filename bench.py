@@ -222,7 +222,22 @@ def profile_pass(steps):
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    log(f"[bench] profile pass: {r}; copy of {a.numel() * 4} bytes x3")
+    log(f"[bench] profile pass: {r}; copy of {a.numel() * 4} bytes x3; read ceiling {read_ceiling():.0f} GB/s")
+
+
+def read_ceiling(nbytes=1 << 30, reps=20):
+    """Device read bandwidth of a plain reduction over nbytes (torch sum), from CUDA/HIP events."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        x.sum()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    return nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
 def main():
@@ -264,6 +279,8 @@ def main():
     if not args.no_fp64:
         fp64 = time_gpu(wl, FP64, table, events, norm, args.steps, args.warmup, args.blocks, args.waves)
         log(f"[bench] fp64: {fp64}")
+    ceiling = read_ceiling()
+    log(f"[bench] plain device read (torch sum of 1 GiB): {ceiling:.0f} GB/s")
     bytes_launch = n_ev * stream_bytes_per_point(4, wl.n_res, "data") + \
         n_nm * stream_bytes_per_point(4, wl.n_res, "norm")
     achieved = bytes_launch / (mixed["stream_kernel_ms"] * 1e-3) / 1e9
@@ -292,7 +309,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_eval<float,2,false>", "bytes_per_launch": bytes_launch,
-                     "kernel_ms": mixed["stream_kernel_ms"]},
+                     "kernel_ms": mixed["stream_kernel_ms"], "measured_read_ceiling_GBs": ceiling,
+                     "frac_of_measured_ceiling": achieved / ceiling},
     }
     if not args.no_serve:
         out["serving"] = serving(args.serve_jobs, MIXED)
