@@ -117,7 +117,10 @@ int mipwa_set_fixed(mipwa_ctx* ctx, const unsigned char* fixed, int n);
  * mass outside its kinematic range). */
 int mipwa_set_params(mipwa_ctx* ctx, const double* theta, int n);
 
-/* -2 ln L and its gradient at the current theta.  grad (nullable) receives P doubles.  Synchronous.
+/* -2 ln L and its gradient at the current theta.  grad (nullable) receives P doubles.  Synchronous:
+ * returns once the device has written the results to pinned host memory (the calling thread polls a
+ * sequence word the finish kernel stores after them; the tail of that kernel may still be retiring on
+ * the context's stream, which every call that replaces device buffers waits for).
  * Errors: E_STATE (no events, norm points or params), E_DOMAIN (non-finite value: *nll = +inf), E_HIP. */
 int mipwa_eval(mipwa_ctx* ctx, double* nll, double* grad);
 

@@ -79,6 +79,20 @@ SIGNATURES = {
 _lib = None
 
 
+def _bind_torch_runtime():
+    """Load PyTorch's HIP runtime before libmipwa when PyTorch is installed.
+
+    PyTorch carries its own libamdhip64 with the same soname as ROCm's.  Loaded first, it satisfies
+    libmipwa's dependency, so the process holds one HIP runtime and device pointers and streams pass
+    between PyTorch and libmipwa.  Loaded the other way round, the process would hold two runtimes
+    and the second to initialise would find no GPU.
+    """
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def load():
     """Load libmipwa.so from the package directory; raises if it has not been built."""
     global _lib
@@ -87,6 +101,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                            "(python -m paper_1703_03284_amd.build)")
+    _bind_torch_runtime()
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name, None)

@@ -3,7 +3,9 @@
     python -m paper_1703_03284_amd.build        (or __graft_entry__.build())
 
 Every source is compiled on each call (the build is the "does it compile" check).  Packed FP32
-instructions are disabled for all device code.
+instructions are disabled for all device code.  Code objects are version 5, which both the ROCm
+runtime and the HIP runtime bundled with PyTorch load (a Python process binds libmipwa to the
+latter; see _lib._bind_torch_runtime).
 """
 from __future__ import annotations
 
@@ -30,7 +32,8 @@ def hipcc() -> str:
 
 
 def flags(defines=()):
-    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
+    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5", "-I", INCLUDE,
+            "-I", CSRC,
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
             *[f"-D{d}" for d in defines]]
 

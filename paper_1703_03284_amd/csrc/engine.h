@@ -70,8 +70,8 @@ struct Job {
   const double* tab64;   // theta[P]
   const double* consts;  // Thomas c'[N-2], 1/pivot[N-2], h[N-1] of the job's knots
   double* out;           // 1 + P results: -2 ln L, gradient (device or mapped host memory)
+  unsigned long long* seq_out;  // when set: the evaluation's sequence number, stored after the results
   double* grec;          // (G_d + G_n) x rs group records
-  double* fin;           // 2 x rs: reduced data record, reduced normalisation record
   double n_ev;
   double c_eps;          // -2 sum ln eff over the events
   int G_d, G_n;
@@ -110,7 +110,12 @@ hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* d_segs, const 
                        hipEvent_t e1 = nullptr);
 // group sums (one block per task (segment, group)) then one finishing block per job
 hipError_t launch_reduce(const Segment* d_segs, const Job* d_jobs, const int2* d_tasks, int n_tasks, int n_jobs,
-                         const ArgTable* args, hipStream_t stream);
+                         const ArgTable* args, hipStream_t stream, unsigned long long seq = 0,
+                         double* out_override = nullptr);
+// Copy `bytes` (a multiple of 16, both addresses 16-byte aligned) from mapped host memory to device
+// memory with a kernel on `stream`.  Per-evaluation tables go up this way, ordered with the kernels
+// that read them like any other kernel on the stream.
+hipError_t launch_upload(void* d_dst, const void* h_src_dev, size_t bytes, hipStream_t stream);
 hipError_t launch_integrals(bool fp64, int R, const Segment* h_seg, const void* w_override,
                             double* d_records, int n_blocks, double* d_out, hipStream_t stream);
 hipError_t launch_eff_lookup(const double* d_s12, const double* d_s13, long long n, const float* d_table,

@@ -49,9 +49,10 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-// Pinned host allocation.
+// Pinned host allocation; a mapped, coherent one also has a device address (dev).
 struct HostBuf {
   void* p = nullptr;
+  void* dev = nullptr;
   size_t bytes = 0;
   HostBuf() = default;
   HostBuf(const HostBuf&) = delete;
@@ -59,16 +60,21 @@ struct HostBuf {
   ~HostBuf() { release(); }
   void release() {
     if (p) (void)hipHostFree(p);
-    p = nullptr;
+    p = dev = nullptr;
     bytes = 0;
   }
   hipError_t alloc(size_t n, bool mapped_coherent = false) {
-    if (n <= bytes && p) return hipSuccess;
+    if (n <= bytes && p && (dev || !mapped_coherent)) return hipSuccess;
     release();
     hipError_t e = hipHostMalloc(&p, n ? n : 16,
                                  mapped_coherent ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault);
-    if (e == hipSuccess) bytes = n;
-    else p = nullptr;
+    if (e == hipSuccess && mapped_coherent) e = hipHostGetDevicePointer(&dev, p, 0);
+    if (e == hipSuccess) {
+      bytes = n;
+    } else {
+      if (p) (void)hipHostFree(p);
+      p = dev = nullptr;
+    }
     return e;
   }
   template <typename T>

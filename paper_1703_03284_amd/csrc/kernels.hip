@@ -14,6 +14,9 @@
 // in registers while the cell does not change, and folds them into a wave-private LDS histogram of
 // spline intervals when it does.  Blocks write fixed-size FP64 records; a second kernel reduces them
 // in a fixed order (bitwise reproducible) and runs the FP64 finish.
+#include <algorithm>
+#include <cstdint>
+
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -380,20 +383,24 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
 }
 
 // ---------------------------------------------------------------------------------------------
-// FP64 finish of one job, run by the block that completes the job's last reduction group:
+// FP64 finish of one job, run by the job's block of k_job_finish once its records are reduced:
 //   -2 ln L = -2 S_data + C_eps + 2 n ln I,  scale = n / I,
 //   spline-polynomial partials -> knot values z and second derivatives M -> z through M = K z,
 //   then the chain rule to (a_k, phi_k), (|c_r|, arg c_r), (m_r, Gamma_r).
 
-__device__ void finish_job(const Job& jb, const ArgTable& targ) {
+// fin: the reduced data record followed by the reduced normalisation record (LDS); kc: the job's
+// Thomas factors and interval widths staged in LDS (the solve below is a serial chain, so its
+// operands must not come from global memory one dependent load at a time).
+__device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fin, const double* kc,
+                           unsigned long long seq, double* out) {
   const int N = jb.N, nint = N - 1, R = jb.R;
-  const double* fd = jb.fin;
-  const double* fn = jb.fin + jb.rs;
+  const double* fd = fin;
+  const double* fn = fin + jb.rs;
   const int s0 = 8 * nint;
   const double I = fn[s0];
   const double scale = jb.n_ev / I;
   const double* th = jb.tab64 ? jb.tab64 : (const double*)((const char*)targ.w + jb.theta_off);
-  const double* thc = jb.consts;         // Thomas factors c'_i of the interior system
+  const double* thc = kc;                // Thomas factors c'_i of the interior system
   const double* thinv = thc + (N - 2);   // 1 / pivot_i
   const double* h = thinv + (N - 2);
   __shared__ double gy[2 * kMaxKnots], gm[2 * kMaxKnots], u[2 * kMaxKnots];
@@ -438,17 +445,18 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ) {
        comp += (blockDim.x >= 128 ? 2 : 1)) {
     const int n = N - 2;
     double prev = 0.0;
+#pragma unroll 8
     for (int i = 0; i < n; ++i) {
       const double a = i > 0 ? h[i] : 0.0;
       prev = (gm[2 * (i + 1) + comp] - a * prev) * thinv[i];
       u[2 * (i + 1) + comp] = prev;
     }
+#pragma unroll 8
     for (int i = n - 2; i >= 0; --i) u[2 * (i + 1) + comp] -= thc[i] * u[2 * (i + 2) + comp];
     u[comp] = 0.0;
     u[2 * (N - 1) + comp] = 0.0;
   }
   __syncthreads();
-  double* out = jb.out;
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
     double yr = gy[2 * k], yi = gy[2 * k + 1];
     // D[k', k] for interior rows k' in {k-1, k, k+1}
@@ -495,6 +503,11 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ) {
   }
   if (threadIdx.x == 0) out[0] = -2.0 * fd[s0] + jb.c_eps + 2.0 * jb.n_ev * log(I);
   __threadfence_system();
+  if (jb.seq_out) {
+    // every thread's results are out; the sequence number tells a polling host they are complete
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(jb.seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 template <typename Real, int R, bool OTF>
@@ -548,7 +561,7 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
 // summed in block order into the job's group record.  No cross-block communication inside a kernel:
 // the kernel boundary after the streaming kernel makes its records visible.
 
-__global__ __launch_bounds__(256) void k_group_sum(const Segment* __restrict__ segs, const Job* __restrict__ jobs,
+__global__ __launch_bounds__(512) void k_group_sum(const Segment* __restrict__ segs, const Job* __restrict__ jobs,
                                                    const int2* __restrict__ tasks) {
   const int2 tk = tasks[blockIdx.x];
   const Segment& sg = segs[tk.x];
@@ -570,18 +583,33 @@ __global__ __launch_bounds__(256) void k_group_sum(const Segment* __restrict__ s
 }
 
 // K4: one block per job: sum the group records in order and run the FP64 finish.
-__global__ __launch_bounds__(256) void k_job_finish(const Job* __restrict__ jobs, ArgTable targ) {
+constexpr int kMaxRecord = 8 * (kMaxKnots - 1) + 1 + 6 * kMaxRes;
+
+__global__ __launch_bounds__(256) void k_job_finish(const Job* __restrict__ jobs, ArgTable targ,
+                                                     unsigned long long seq, double* out_override) {
+  __shared__ double fin[2 * kMaxRecord];
+  __shared__ double kc[3 * kMaxKnots];
   const Job jb = jobs[blockIdx.x];
   const int rs = jb.rs;
-  for (int f = threadIdx.x; f < rs; f += blockDim.x) {
-    double d = 0.0, q = 0.0;
-    for (int k = 0; k < jb.G_d; ++k) d += jb.grec[(long long)k * rs + f];
-    for (int k = 0; k < jb.G_n; ++k) q += jb.grec[(long long)(jb.G_d + k) * rs + f];
-    jb.fin[f] = d;
-    jb.fin[rs + f] = q;
+  // field f < rs of the data groups, then of the normalisation groups; the group loads of one field
+  // are issued eight at a time and summed in group order
+  for (int f = threadIdx.x; f < 2 * rs; f += blockDim.x) {
+    const bool nrm = f >= rs;
+    const int G = nrm ? jb.G_n : jb.G_d;
+    const double* p = jb.grec + (long long)(nrm ? jb.G_d : 0) * rs + (nrm ? f - rs : f);
+    double s = 0.0;
+    for (int k0 = 0; k0 < G; k0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = k0 + k < G ? p[(long long)(k0 + k) * rs] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    fin[f] = s;
   }
+  for (int i = threadIdx.x; i < 3 * jb.N - 5; i += blockDim.x) kc[i] = jb.consts[i];
   __syncthreads();
-  finish_job(jb, targ);
+  finish_job(jb, targ, fin, kc, seq, out_override ? out_override : jb.out);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -897,13 +925,30 @@ hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const in
 }
 
 hipError_t launch_reduce(const Segment* segs, const Job* jobs, const int2* tasks, int n_tasks, int n_jobs,
-                         const ArgTable* targ, hipStream_t st) {
+                         const ArgTable* targ, hipStream_t st,
+                         unsigned long long seq, double* out_override) {
   (void)hipGetLastError();
   static const ArgTable empty{};
-  k_group_sum<<<n_tasks, 256, 0, st>>>(segs, jobs, tasks);
+  k_group_sum<<<n_tasks, 512, 0, st>>>(segs, jobs, tasks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_job_finish<<<n_jobs, 256, 0, st>>>(jobs, targ ? *targ : empty);
+  k_job_finish<<<n_jobs, 256, 0, st>>>(jobs, targ ? *targ : empty, seq, out_override);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_upload(const uint4* __restrict__ src, uint4* __restrict__ dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_upload(void* d_dst, const void* h_src_dev, size_t bytes, hipStream_t st) {
+  (void)hipGetLastError();
+  if (bytes % 16 || (reinterpret_cast<uintptr_t>(d_dst) | reinterpret_cast<uintptr_t>(h_src_dev)) % 16)
+    return hipErrorInvalidValue;
+  const long long n = (long long)(bytes / 16);
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 64);
+  k_upload<<<blocks, 256, 0, st>>>(static_cast<const uint4*>(h_src_dev), static_cast<uint4*>(d_dst), n);
   return hipGetLastError();
 }
 

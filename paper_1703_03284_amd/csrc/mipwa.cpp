@@ -5,8 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <immintrin.h>
 #include <string>
 #include <vector>
 
@@ -38,10 +40,15 @@ int default_blocks(int device) {
 
 }  // namespace
 
+// Sequence numbers of synchronous evaluations, unique in the process.
+static std::atomic<unsigned long long> g_eval_seq{0};
+
 // ---- device descriptors and tables -----------------------------------------------------------
 
 int mipwa_ctx::rebuild_launch() {
   mipwa_ctx* ctx = this;
+  // the buffers below are replaced: nothing queued may still use them
+  HIPCHK(hipStreamSynchronize(stream), "stream sync");
   const int waves = waves_cfg ? waves_cfg : (fp64 ? 4 : 8);
   waves_eff = waves;
   const int total_tiles = ev.n_tiles + nm.n_tiles;
@@ -55,7 +62,6 @@ int mipwa_ctx::rebuild_launch() {
   const int G_d = n_groups(nb_d), G_n = n_groups(nb_n);
   HIPCHK(d_records.alloc((size_t)B * rs * sizeof(double)), "records allocation");
   HIPCHK(d_grec.alloc((size_t)(G_d + G_n) * rs * sizeof(double)), "group records allocation");
-  HIPCHK(d_fin.alloc(2 * (size_t)rs * sizeof(double)), "finish scratch allocation");
   std::vector<int2> tasks;
   for (int g = 0; g < G_d; ++g) tasks.push_back(int2{0, g});
   for (int g = 0; g < G_n; ++g) tasks.push_back(int2{1, g});
@@ -97,9 +103,8 @@ int mipwa_ctx::rebuild_launch() {
     const double* t64 = d_blob.as<double>() + tab64_off / sizeof(double);
     jb[k].tab64 = use_arg ? nullptr : t64;
     jb[k].theta_off = arg_theta_off;
-    jb[k].consts = t64 + mh.P;
+    jb[k].consts = d_blob.as<double>() + consts_off / sizeof(double);
     jb[k].grec = d_grec.as<double>();
-    jb[k].fin = d_fin.as<double>();
     jb[k].n_ev = (double)ev.n;
     jb[k].c_eps = ev.c_eps;
     jb[k].G_d = G_d;
@@ -110,7 +115,9 @@ int mipwa_ctx::rebuild_launch() {
     jb[k].otf = otf ? 1 : 0;
   }
   jb[0].out = h_out_dev;
+  jb[0].seq_out = reinterpret_cast<unsigned long long*>(h_out_dev + 1 + mh.P);
   jb[1].out = d_out.as<double>();
+  jb[1].seq_out = nullptr;
   HIPCHK(hipMemcpy(d_job.p, jb, sizeof(jb), hipMemcpyHostToDevice), "job upload");
   launch_dirty = false;
   return MIPWA_OK;
@@ -118,8 +125,9 @@ int mipwa_ctx::rebuild_launch() {
 
 int mipwa_ctx::stage_params() {
   mipwa_ctx* ctx = this;
-  // wait until the previous upload has left the pinned staging buffer
-  HIPCHK(hipEventSynchronize(ev_staged), "staging wait");
+  // wait until the previous upload has left the staging buffer (evaluations whose tables travel in
+  // the kernel arguments upload nothing; mipwa_integrals waits for its own upload before returning)
+  if (!use_arg) HIPCHK(hipEventSynchronize(ev_staged), "staging wait");
   const int nint = mh.N - 1, R = mh.R;
   std::vector<double> tab(table_words(nint, R));
   mh.poly_table(theta.data(), tab.data());
@@ -167,11 +175,16 @@ int mipwa_ctx::ensure_cache(hipStream_t st) {
   return MIPWA_OK;
 }
 
-int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed) {
+int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigned long long s, double* out) {
   mipwa_ctx* ctx = this;
-  if (timed) HIPCHK(hipEventRecord(ev_t0, st), "event");
+  if (timed) {
+    // the events are about to be recorded again: take the previous timed evaluation's times first
+    int rc = fold_timing();
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(ev_t0, st), "event");
+  }
   if (!use_arg) {
-    HIPCHK(hipMemcpyAsync(d_blob.p, h_blob.p, upload_bytes, hipMemcpyHostToDevice, st), "parameter upload");
+    HIPCHK(launch_upload(d_blob.p, h_blob.dev, upload16(), st), "parameter upload");
     HIPCHK(hipEventRecord(ev_staged, st), "event");
   }
   // with use_arg the table and theta travel in the kernel arguments (copied at the launch)
@@ -180,7 +193,7 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed) {
                      use_arg ? &h_args : nullptr, st, timed ? ev_t1 : nullptr, timed ? ev_t2 : nullptr),
          "likelihood kernel");
   HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), d_tasks.as<int2>(), n_tasks, 1,
-                       use_arg ? &h_args : nullptr, st),
+                       use_arg ? &h_args : nullptr, st, s, out),
          "reduction kernels");
   if (timed) HIPCHK(hipEventRecord(ev_t3, st), "event");
   return MIPWA_OK;
@@ -202,23 +215,51 @@ int mipwa_ctx::prepare_eval(hipStream_t st) {
   return MIPWA_OK;
 }
 
-int mipwa_ctx::run_sync_eval() {
+// Wait for the finish kernel to publish sequence number s after the results in mapped host memory.
+// Spinning on that word returns as soon as the results land, without waiting for the stream's
+// completion signal; the stream is queried now and then so that a failed launch is still reported.
+int mipwa_ctx::wait_result(unsigned long long s) {
+  const unsigned long long* word = reinterpret_cast<const unsigned long long*>(h_out.as<double>() + 1 + mh.P);
+  for (unsigned long long it = 1;; ++it) {
+    if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == s) return MIPWA_OK;
+    if ((it & 1023) == 0) {
+      const hipError_t q = hipStreamQuery(stream);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == s) return MIPWA_OK;
+        return fail(MIPWA_E_HIP, "the evaluation ended without publishing its result");
+      }
+      if (q != hipErrorNotReady) return fail(MIPWA_E_HIP, std::string("evaluation failed: ") + hipGetErrorString(q));
+    }
+    _mm_pause();
+  }
+}
+
+int mipwa_ctx::fold_timing() {
   mipwa_ctx* ctx = this;
+  if (!timing_unread) return MIPWA_OK;
+  timing_unread = false;
+  HIPCHK(hipEventSynchronize(ev_t3), "event sync");
+  float a = 0, b = 0;
+  if (hipEventElapsedTime(&a, ev_t0, ev_t3) == hipSuccess && hipEventElapsedTime(&b, ev_t1, ev_t2) == hipSuccess) {
+    t_count += 1;
+    t_total += a;
+    t_stream += b;
+  }
+  (void)hipGetLastError();
+  return MIPWA_OK;
+}
+
+int mipwa_ctx::run_sync_eval() {
   int rc = prepare_eval(stream);
   if (rc) return rc;
-  rc = enqueue_kernels(stream, true, timing_on);
+  // numbers are unique in the process: pinned memory handed back by a destroyed context may still
+  // hold one of its sequence numbers
+  const unsigned long long s = seq = g_eval_seq.fetch_add(1, std::memory_order_relaxed) + 1;
+  rc = enqueue_kernels(stream, true, timing_on, s);
   if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(stream), "stream sync");
-  if (timing_on) {
-    float a = 0, b = 0;
-    if (hipEventElapsedTime(&a, ev_t0, ev_t3) == hipSuccess && hipEventElapsedTime(&b, ev_t1, ev_t2) == hipSuccess) {
-      t_count += 1;
-      t_total += a;
-      t_stream += b;
-      timing_pending = true;
-    }
-    (void)hipGetLastError();
-  }
+  rc = wait_result(s);
+  if (rc) return rc;
+  if (timing_on) timing_unread = timing_pending = true;
   return MIPWA_OK;
 }
 
@@ -272,18 +313,20 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
   const size_t tbytes = table_words(mh.N - 1, mh.R) * real;
   ctx->tab64_off = (tbytes + 255) / 256 * 256;
   ctx->upload_bytes = ctx->tab64_off + mh.P * sizeof(double);
+  ctx->consts_off = ctx->upload16();  // the per-evaluation upload never reaches the constants
   ctx->arg_theta_off = (int)((tbytes + 7) / 8 * 8);
   ctx->use_arg = ctx->arg_theta_off + mh.P * sizeof(double) <= (size_t)kArgBytes;
-  const size_t blob = ctx->tab64_off + ((size_t)mh.P + 2 * (size_t)mh.N + mh.N) * sizeof(double);
-  if (ctx->d_blob.alloc(blob) != hipSuccess || ctx->h_blob.alloc(ctx->upload_bytes) != hipSuccess ||
+  const size_t blob = ctx->consts_off + 3 * (size_t)mh.N * sizeof(double);
+  if (ctx->d_blob.alloc(blob) != hipSuccess || ctx->h_blob.alloc(ctx->upload16(), true) != hipSuccess ||
       ctx->d_out.alloc((1 + mh.P) * sizeof(double)) != hipSuccess ||
-      ctx->h_out.alloc((1 + mh.P) * sizeof(double), true) != hipSuccess ||
+      ctx->h_out.alloc((2 + mh.P) * sizeof(double), true) != hipSuccess ||
       hipHostGetDevicePointer((void**)&ctx->h_out_dev, ctx->h_out.p, 0) != hipSuccess ||
       ctx->d_job.alloc(2 * sizeof(Job)) != hipSuccess) {
     delete ctx;
     return MIPWA_E_NOMEM;
   }
-  // constant part of the FP64 table after theta: Thomas factors of the interior spline system, h
+  std::memset(ctx->h_out.p, 0, (2 + mh.P) * sizeof(double));
+  // constant part of the FP64 table (at consts_off): Thomas factors of the interior spline system, h
   const int ni = mh.N - 2;
   std::vector<double> cst(2 * (size_t)ni + mh.N - 1);
   for (int i = 0; i < ni; ++i) {
@@ -291,7 +334,7 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
     cst[ni + i] = 1.0 / mh.th_d[i];
   }
   std::copy(mh.h.begin(), mh.h.end(), cst.begin() + 2 * ni);
-  if (hipMemcpy(ctx->d_blob.as<char>() + ctx->tab64_off + mh.P * sizeof(double), cst.data(),
+  if (hipMemcpy(ctx->d_blob.as<char>() + ctx->consts_off, cst.data(),
                 cst.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     delete ctx;
     return MIPWA_E_HIP;
@@ -407,11 +450,9 @@ int mipwa_eval_async(mipwa_ctx* ctx, void* stream, double* d_out) {
   hipStream_t st = (hipStream_t)stream;
   int rc = ctx->prepare_eval(st);
   if (rc) return rc;
-  rc = ctx->enqueue_kernels(st, false, true);
+  rc = ctx->enqueue_kernels(st, false, true, 0, d_out);
   if (rc) return rc;
   ctx->timing_pending = true;
-  HIPCHK(hipMemcpyAsync(d_out, ctx->d_out.p, (1 + ctx->mh.P) * sizeof(double), hipMemcpyDeviceToDevice, st),
-         "result copy");
   return MIPWA_OK;
 }
 
@@ -431,6 +472,7 @@ int mipwa_last_timing(const mipwa_ctx* cctx, double* total_ms, double* stream_ms
 int mipwa_set_timing(mipwa_ctx* ctx, int on) {
   if (!ctx) return MIPWA_E_INVAL;
   ctx->timing_on = on != 0;
+  ctx->timing_unread = false;
   ctx->t_count = 0;
   ctx->t_total = ctx->t_stream = 0.0;
   return MIPWA_OK;
@@ -438,6 +480,7 @@ int mipwa_set_timing(mipwa_ctx* ctx, int on) {
 
 int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_ms, double* mean_stream_ms) {
   if (!ctx) return MIPWA_E_INVAL;
+  if (int rc = const_cast<mipwa_ctx*>(ctx)->fold_timing()) return rc;
   const double n = ctx->t_count > 0 ? (double)ctx->t_count : 1.0;
   if (count) *count = ctx->t_count;
   if (mean_total_ms) *mean_total_ms = ctx->t_total / n;
@@ -458,7 +501,7 @@ int mipwa_integrals(mipwa_ctx* ctx, int with_eff, double* Ijk) {
   }
   int rc = ctx->stage_params();
   if (rc) return rc;
-  HIPCHK(hipMemcpyAsync(ctx->d_blob.p, ctx->h_blob.p, ctx->upload_bytes, hipMemcpyHostToDevice, st), "upload");
+  HIPCHK(launch_upload(ctx->d_blob.p, ctx->h_blob.dev, ctx->upload16(), st), "upload");
   HIPCHK(hipEventRecord(ctx->ev_staged, st), "event");
   // the normalisation segment with its cache valid at the current shapes
   Segment sg;

@@ -3,11 +3,13 @@
 // Each submitted job is a maximum-likelihood fit (the fit of Sec. 2 / Sec. 4 on a toy sample) of its
 // own events against a normalisation sample shared by the server.  Jobs wait in a queue until their
 // device footprint fits the HBM budget; an admitted job loads its events (cell sort, resonance cache)
-// on its own stream and thread, then runs the BFGS fit in that thread.  Every evaluation it asks for
-// is posted to the scheduler, which gathers the pending evaluations of all active jobs into one launch
-// of the streaming kernel (one data segment and one normalisation segment per job; the normalisation
-// segments of jobs sharing a knot grid read the same point arrays, and their blocks are interleaved
-// so that the same tiles are read close together in time).  Jobs that become active while a step
+// and builds the resonance cache of the shared normalisation points at its own masses and widths, on
+// its own stream and thread, then runs the BFGS fit in that thread.  The normalisation points are
+// cell-sorted once per knot grid and shared.  Every evaluation a job asks for is posted to the
+// scheduler, which gathers the pending evaluations of all active jobs into one launch of the
+// streaming kernel (one data segment and one normalisation segment per job; the normalisation
+// segments of jobs sharing a knot grid read the same coordinates, weights and tiles, and their blocks
+// are interleaved so that the same tiles are read close together in time).  Jobs that become active while a step
 // runs join the next step.  A job's block count depends only on its own sizes, so its reduction
 // order, and therefore its result, is bitwise the same alone or in any mix.
 #include <hip/hip_runtime.h>
@@ -17,6 +19,9 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -44,10 +49,11 @@ int seg_blocks(int n_tiles) {
   return std::min(std::max(b, 1), kMaxSegBlocks);
 }
 
+// The shared normalisation sample sorted for one knot grid: local spline coordinates, weights and
+// tiles.  The resonance amplitudes depend on each job's shapes and live with the job.
 struct NormSet {
-  std::vector<double> key;  // kinematics, knots, resonance constants and shapes
-  ModelHost mh;
-  PointSet ps;
+  std::vector<double> key;  // kinematics and knots
+  PointSet ps;              // no resonance cache of its own
   int nb = 0;
   size_t bytes = 0;
 };
@@ -67,7 +73,8 @@ struct SJob {
   PointSet ev;
   NormSet* norm = nullptr;
   int nb_d = 0, G_d = 0, G_n = 0, rs = 0;
-  DevBuf d_rec, d_grec, d_fin, d_consts, d_tab;
+  DevBuf d_rec, d_grec, d_consts, d_tab;
+  DevBuf d_ncache;  // resonance amplitudes of the shared normalisation points at this job's shapes
   size_t bytes = 0;
   JobState state = QUEUED;
   int status = MIPWA_OK;
@@ -84,15 +91,9 @@ struct SJob {
   FitOut result;
 };
 
-std::vector<double> norm_key(const ModelHost& mh, const std::vector<double>& theta) {
-  std::vector<double> k = {mh.M, mh.m1, mh.m2, mh.m3, mh.rD, (double)mh.N, (double)mh.R};
+std::vector<double> norm_key(const ModelHost& mh) {
+  std::vector<double> k = {mh.M, mh.m1, mh.m2, mh.m3, mh.rD, (double)mh.N};
   k.insert(k.end(), mh.knots.begin(), mh.knots.end());
-  for (int r = 0; r < mh.R; ++r) {
-    k.push_back(mh.res[r].spin);
-    k.push_back(mh.res[r].radius);
-    k.push_back(theta[2 * mh.N + 2 * mh.R + 2 * r]);
-    k.push_back(theta[2 * mh.N + 2 * mh.R + 2 * r + 1]);
-  }
   return k;
 }
 
@@ -156,7 +157,7 @@ struct mipwa_server {
   long long steps = 0;
   double batch_sum = 0;
   bool any_submit = false;
-  Clock::time_point t_first_submit, t_last_done;
+  Clock::time_point t_first_submit, t_last_done, t_create = Clock::now();
   std::vector<double> latencies;
   HostBuf h_batch, h_res;
   DevBuf d_batch;
@@ -172,6 +173,23 @@ struct mipwa_server {
 static void serve_worker(mipwa_server* S, SJob* J);
 
 namespace {
+
+// Event trace on stderr when MIPWA_SERVE_TRACE is set: job admission, end of loading, completion,
+// and every 256th batched step (seconds since the server was created).
+bool trace_on() {
+  static const bool on = std::getenv("MIPWA_SERVE_TRACE") != nullptr;
+  return on;
+}
+
+void trace(const mipwa_server* S, const char* fmt, ...) {
+  if (!trace_on()) return;
+  char msg[256];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[serve %.4f] %s\n", std::chrono::duration<double>(Clock::now() - S->t_create).count(), msg);
+}
 
 void admit(mipwa_server* S) {
   while (!S->queue.empty()) {
@@ -189,35 +207,26 @@ void admit(mipwa_server* S) {
     S->peak = std::max(S->peak, S->used);
     S->running += 1;
     J->state = LOADING;
+    trace(S, "admit job %lld: %lld events, %d knots, used %.2f GB", (long long)J->id, J->n, J->mh.N, S->used / 1e9);
     J->worker = std::thread(serve_worker, S, J);
   }
 }
 
-NormSet* get_norm(mipwa_server* S, const ModelHost& mh, const std::vector<double>& theta, hipStream_t st,
-                  std::string& err, int& rc) {
+NormSet* get_norm(mipwa_server* S, const ModelHost& mh, hipStream_t st, std::string& err, int& rc) {
   std::lock_guard<std::mutex> g(S->norm_mu);
-  const std::vector<double> key = norm_key(mh, theta);
+  const std::vector<double> key = norm_key(mh);
   for (auto& ns : S->norms)
     if (ns->key == key) return ns.get();
   auto ns = std::make_unique<NormSet>();
   ns->key = key;
-  ns->mh = mh;
   EffTable none;
   rc = load_points(mh, S->fp64, 1, S->n12.data(), S->n13.data(), S->nw.data(), nullptr, (long long)S->n12.size(),
                    none, st, ns->ps, err);
   if (rc) return nullptr;
-  DevBuf dr;
-  Segment sg = cache_segment(ns->ps, mh.N - 1);
-  if (mh.upload_res64(theta.data(), dr) != MIPWA_OK ||
-      launch_cache(S->fp64, mh.R, &sg, dr.as<double>(), mh.kin64, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess) {
-    err = "normalisation cache build failed";
-    rc = MIPWA_E_HIP;
-    return nullptr;
-  }
+  ns->ps.cache.release();
   const size_t real = S->fp64 ? 8 : 4;
   ns->nb = seg_blocks(ns->ps.n_tiles);
-  ns->bytes = (size_t)ns->ps.n * ((4 + 2 * mh.R) * real + 16) + (size_t)ns->ps.n_tiles * sizeof(Tile);
+  ns->bytes = (size_t)ns->ps.n * (4 * real + 16) + (size_t)ns->ps.n_tiles * sizeof(Tile);
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->used += ns->bytes;
@@ -233,6 +242,7 @@ void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
   J->status = status;
   J->err = err;
   J->t_done = Clock::now();
+  trace(S, "job %lld done: status %d, %d evaluations", (long long)J->id, status, J->result.n_eval);
   if (status == MIPWA_OK || status == MIPWA_E_NOCONV) {
     S->latencies.push_back(std::chrono::duration<double>(J->t_done - J->t_submit).count());
     S->t_last_done = J->t_done;
@@ -240,8 +250,8 @@ void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
   J->ev = PointSet();
   J->d_rec.release();
   J->d_grec.release();
-  J->d_fin.release();
   J->d_consts.release();
+  J->d_ncache.release();
   S->used -= J->bytes;
   S->running -= 1;
   S->cv_done.notify_all();
@@ -263,10 +273,13 @@ static void serve_worker(mipwa_server* S, SJob* J) {
   J->s12 = std::vector<double>();
   J->s13 = std::vector<double>();
   NormSet* ns = nullptr;
-  if (!rc) ns = get_norm(S, J->mh, J->theta0, st, err, rc);
+  if (!rc) ns = get_norm(S, J->mh, st, err, rc);
   if (!rc) {
-    // resonance cache of the events at the job's (fixed) shapes; per-job reduction scratch
+    // resonance caches of the events and of the shared normalisation points at the job's (fixed)
+    // shapes; per-job reduction scratch
     Segment sg = cache_segment(J->ev, J->mh.N - 1);
+    Segment sgn = cache_segment(ns->ps, J->mh.N - 1);
+    const size_t real = S->fp64 ? 8 : 4;
     J->norm = ns;
     J->nb_d = seg_blocks(J->ev.n_tiles);
     J->G_d = n_groups(J->nb_d);
@@ -281,15 +294,20 @@ static void serve_worker(mipwa_server* S, SJob* J) {
     std::copy(J->mh.h.begin(), J->mh.h.end(), cst.begin() + 2 * ni);
     if (J->mh.upload_res64(J->theta0.data(), J->d_tab) != MIPWA_OK ||
         J->d_rec.alloc((size_t)(J->nb_d + ns->nb) * J->rs * 8) ||
-        J->d_grec.alloc((size_t)(J->G_d + J->G_n) * J->rs * 8) || J->d_fin.alloc(2 * (size_t)J->rs * 8) ||
-        J->d_consts.alloc(cst.size() * 8)) {
+        J->d_grec.alloc((size_t)(J->G_d + J->G_n) * J->rs * 8) ||
+        J->d_consts.alloc(cst.size() * 8) ||
+        J->d_ncache.alloc((size_t)std::max(J->mh.R, 1) * 2 * ns->ps.n * real)) {
       rc = MIPWA_E_NOMEM;
       err = "device allocation for a job failed";
-    } else if (hipMemcpy(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-               launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
-               hipStreamSynchronize(st) != hipSuccess) {
-      rc = MIPWA_E_HIP;
-      err = "loading a job failed";
+    } else {
+      sgn.cache = J->d_ncache.p;
+      if (hipMemcpy(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+          launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
+          launch_cache(S->fp64, J->mh.R, &sgn, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        rc = MIPWA_E_HIP;
+        err = "loading a job failed";
+      }
     }
     J->d_tab.release();
   }
@@ -301,6 +319,7 @@ static void serve_worker(mipwa_server* S, SJob* J) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     J->state = ACTIVE;
+    trace(S, "job %lld active", (long long)J->id);
     S->cv_sched.notify_all();
   }
   const ModelHost& mh = J->mh;
@@ -388,7 +407,7 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
       o_th[j] = o_tab[j] + toff;
       max_nint = std::max(max_nint, js[j]->mh.N - 1);
     }
-    if (S->h_batch.alloc(off) != hipSuccess || S->d_batch.alloc(off) != hipSuccess)
+    if (S->h_batch.alloc(off, true) != hipSuccess || S->d_batch.alloc(off) != hipSuccess)
       return S->fail(MIPWA_E_NOMEM, "batch buffer allocation failed");
     char* hb = S->h_batch.as<char>();
     char* db = S->d_batch.as<char>();
@@ -408,7 +427,7 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
         s.tt = ps[k]->tt.p;
         s.ss = ps[k]->ss.p;
         s.w = k ? ps[k]->w.p : nullptr;
-        s.cache = ps[k]->cache.p;
+        s.cache = k ? J->d_ncache.p : ps[k]->cache.p;
         s.tiles = ps[k]->tiles.as<Tile>();
         s.table = db + o_tab[j];
         s.records = J->d_rec.as<double>() + (size_t)(k ? J->nb_d : 0) * J->rs;
@@ -426,7 +445,6 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
       q.consts = J->d_consts.as<double>();
       q.out = S->h_res_dev + res_of[J];
       q.grec = J->d_grec.as<double>();
-      q.fin = J->d_fin.as<double>();
       q.n_ev = (double)J->ev.n;
       q.c_eps = 0.0;
       q.G_d = J->G_d;
@@ -436,7 +454,7 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
       q.rs = J->rs;
       q.otf = 0;
     }
-    if (hipMemcpyAsync(db, hb, off, hipMemcpyHostToDevice, S->stream) != hipSuccess)
+    if (launch_upload(db, S->h_batch.dev, off, S->stream) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batch upload failed");
     const ModelHost& mh0 = js[0]->mh;
     if (launch_eval(S->fp64, R, false, reinterpret_cast<const Segment*>(db + o_seg),
@@ -513,6 +531,7 @@ void sched_loop(mipwa_server* S) {
     }
     S->steps += 1;
     S->batch_sum += (double)batch.size();
+    if (S->steps % 256 == 1) trace(S, "step %lld: batch %zu of %d active", S->steps, batch.size(), n_pending().second);
   }
 }
 
@@ -584,6 +603,7 @@ int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double*
   J->hessian = opts ? opts->hessian != 0 : false;
   const size_t real = S->fp64 ? 8 : 4;
   J->bytes = (size_t)n * ((2 + 2 * R) * real + 16) + (size_t)(n / kTile + 1) * 2 * sizeof(Tile) +
+             S->n12.size() * 2 * (size_t)std::max(R, 1) * real +
              (size_t)(2 * kMaxSegBlocks + 32) * record_size(N - 1, R, false) * 8;
   if (J->bytes > S->budget) return S->fail(MIPWA_E_NOMEM, "the job alone exceeds the HBM budget");
   std::lock_guard<std::mutex> lk(S->mu);

@@ -107,6 +107,43 @@ def test_mass_width_gradient_vs_finite_differences():
         assert abs(fd - g[p]) <= 1e-4 * max(1.0, abs(g[p])) + 2e-5 * np.abs(g).max(), (p, fd, g[p])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_consecutive_evaluations_see_their_own_parameters(prec):
+    """Back-to-back evaluations on one context, each at new knot, coefficient and shape values.  The
+    FP64 tables of 50 knots and three floated resonances exceed the kernel-argument space and go up
+    through device memory; the mixed ones travel in the arguments."""
+    wl = synth.C4
+    prob = make_problem(wl, 2000, 10000, seed=12)
+    ctx = prob.context(_prec(prec))
+    ctx.set_fixed(wl.fixed())
+    tol = FP64_NLL if prec == "fp64" else MIX_NLL
+    rng = np.random.Generator(np.random.PCG64(77))
+    N, R = wl.n_knots, wl.n_res
+    for k in range(4):
+        th = prob.theta.copy()
+        th[:2 * N + 2 * R] *= 1.0 + 0.01 * rng.standard_normal(2 * N + 2 * R)
+        th[2 * N + 2 * R::2] += 1e-3 * k          # masses
+        th[2 * N + 2 * R + 1::2] *= 1.0 + 0.01 * k  # widths
+        v, _ = ctx.eval(th)
+        v_o, _ = prob.oracle(theta=th)
+        assert rel(v, v_o) <= tol, (k, v, v_o)
+
+
+def test_first_evaluation_of_a_new_context_is_its_own():
+    """A context created after another of the same size was destroyed returns its own results on its
+    first evaluation (its pinned result buffer may reuse the old one's memory)."""
+    wl = synth.C1
+    a = make_problem(wl, 2000, 10000, seed=21)
+    b = make_problem(wl, 2500, 10000, seed=22)
+    for _ in range(2):
+        ctx = a.context(_prec("mixed"))
+        ctx.eval()
+        ctx.close()
+    ctx = b.context(_prec("mixed"))
+    v, _ = ctx.eval()
+    assert rel(v, b.oracle()[0]) <= MIX_NLL
+
+
 def test_cache_rebuilt_when_shapes_change():
     wl = synth.C2
     prob = make_problem(wl, 2000, 10000, seed=8)

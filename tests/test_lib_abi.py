@@ -61,3 +61,17 @@ def test_product_path_has_no_oracle_dependency():
 @pytest.mark.parametrize("name", ["kernels.hip", "host.cpp", "mipwa.cpp", "fit.cpp", "gen.cpp"])
 def test_sources_present(name):
     assert os.path.exists(os.path.join(ROOT, "paper_1703_03284_amd", "csrc", name))
+
+
+def test_one_hip_runtime_per_process():
+    # the binding loads PyTorch's HIP runtime first, so libmipwa binds to it instead of mapping a
+    # second libamdhip64 (two runtimes in one process: the second to initialise finds no GPU)
+    import subprocess
+    import sys
+    code = ("import paper_1703_03284_amd._lib as L; L.load(); "
+            "maps = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}; "
+            "print(len(maps)); print(*sorted(maps))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split()[0] == "1", r.stdout
