@@ -39,7 +39,7 @@ struct mipwa_ctx {
   mipwa::HostBuf h_out;          // mapped, coherent: the finish writes the results here
   double* h_out_dev = nullptr;   // device view of h_out
   mipwa::Segment h_segs[2];
-  int blocks_cfg = 512, waves_cfg = 0, waves_eff = 8;
+  int blocks_cfg = 512, waves_cfg = 0, waves_eff = 4;
   int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0, n_tasks = 0;
   bool launch_dirty = true;
 

@@ -49,7 +49,7 @@ int mipwa_ctx::rebuild_launch() {
   mipwa_ctx* ctx = this;
   // the buffers below are replaced: nothing queued may still use them
   HIPCHK(hipStreamSynchronize(stream), "stream sync");
-  const int waves = waves_cfg ? waves_cfg : (fp64 ? 4 : 8);
+  const int waves = waves_cfg ? waves_cfg : 4;
   waves_eff = waves;
   const int total_tiles = ev.n_tiles + nm.n_tiles;
   const int B = std::max(2, std::min(blocks_cfg, std::max(2, total_tiles / (2 * waves))));
@@ -362,7 +362,7 @@ int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves) {
   if (!ctx) return MIPWA_E_INVAL;
   if (blocks < 0 || waves < 0 || waves > 8) return ctx->fail(MIPWA_E_INVAL, "waves per block must be 1..8");
   ctx->blocks_cfg = blocks ? blocks : default_blocks(ctx->device);
-  ctx->waves_cfg = waves;  // 0: 8 waves per block for FP32 streams, 4 for FP64
+  ctx->waves_cfg = waves;  // 0: 4 waves per block
   ctx->launch_dirty = true;
   return MIPWA_OK;
 }

@@ -41,8 +41,8 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-constexpr int kServeWaves = 8;
-constexpr int kMaxSegBlocks = 256;
+constexpr int kServeWaves = 4;
+constexpr int kMaxSegBlocks = 512;
 
 int seg_blocks(int n_tiles) {
   const int b = (n_tiles + 2 * kServeWaves - 1) / (2 * kServeWaves);
