@@ -39,14 +39,20 @@ struct mipwa_ctx {
   mipwa::HostBuf h_out;          // mapped, coherent: the finish writes the results here
   double* h_out_dev = nullptr;   // device view of h_out
   mipwa::Segment h_segs[2];
+  mipwa::Job h_jobs[2];          // host copies: the finish takes the job descriptor by value
   int blocks_cfg = 512, waves_cfg = 0, waves_eff = 4;
   int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0, n_tasks = 0;
   bool launch_dirty = true;
 
-  hipEvent_t ev_staged = nullptr, ev_t0 = nullptr, ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;
+  // Timing events: two sets [before the sweep, sweep start, sweep end, after the finish] used in
+  // turn, so that an evaluation reads the previous one's times after its own launches are queued.
+  hipEvent_t ev_staged = nullptr;
+  hipEvent_t ev_t[2][4] = {};
+  int ev_cur = 0;                 // set the next timed evaluation records into
+  int ev_last = 0;                // set of the last timed evaluation
+  bool set_unread[2] = {false, false};
   bool timing_pending = false;
   bool timing_on = false;
-  bool timing_unread = false;     // the last timed synchronous evaluation is not yet in the totals
   unsigned long long seq = 0;     // sequence number of the last synchronous evaluation
   long long t_count = 0;
   double t_total = 0.0, t_stream = 0.0;
@@ -55,8 +61,10 @@ struct mipwa_ctx {
   std::string err;
 
   ~mipwa_ctx() {
-    for (hipEvent_t e : {ev_staged, ev_t0, ev_t1, ev_t2, ev_t3})
-      if (e) (void)hipEventDestroy(e);
+    if (ev_staged) (void)hipEventDestroy(ev_staged);
+    for (auto& set : ev_t)
+      for (hipEvent_t e : set)
+        if (e) (void)hipEventDestroy(e);
     if (stream) (void)hipStreamDestroy(stream);
   }
 
@@ -69,6 +77,7 @@ struct mipwa_ctx {
   int enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigned long long s = 0, double* out = nullptr);
   size_t upload16() const { return (upload_bytes + 15) / 16 * 16; }
   int wait_result(unsigned long long s);
-  int fold_timing();
+  int fold_timing(int set);
+  int fold_all_timing();
   int run_sync_eval();
 };

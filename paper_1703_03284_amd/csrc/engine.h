@@ -19,6 +19,8 @@ static_assert(kTile % 64 == 0, "tiles hold whole wavefronts");
 constexpr int kMaxWaves = 16;
 constexpr int kMaxRes = 4;
 constexpr int kMaxKnots = 128;
+// Doubles of the per-model constants: Thomas factors and interval widths.
+__host__ __device__ inline int consts_words(int N) { return 3 * N - 5; }
 // Words per resonance in the evaluation table:
 // m^2, kappa, delta, rho^2, L, m, dln(kappa)/dm, d(delta)/dm, d(delta)/dGamma, unused.
 constexpr int kResWords = 10;
@@ -111,7 +113,7 @@ hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* d_segs, const 
 // group sums (one block per task (segment, group)) then one finishing block per job
 hipError_t launch_reduce(const Segment* d_segs, const Job* d_jobs, const int2* d_tasks, int n_tasks, int n_jobs,
                          const ArgTable* args, hipStream_t stream, unsigned long long seq = 0,
-                         double* out_override = nullptr);
+                         double* out_override = nullptr, const Job* single = nullptr);
 // Copy `bytes` (a multiple of 16, both addresses 16-byte aligned) from mapped host memory to device
 // memory with a kernel on `stream`.  Per-evaluation tables go up this way, ordered with the kernels
 // that read them like any other kernel on the stream.

@@ -495,9 +495,9 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
   // M = T^-1 D z on the interior knots, T symmetric tridiagonal: the z-partials through M are
   // D^T T^-1 g_M.  One Thomas solve per component (re on wave 0, im on wave 1, or both on thread 0
   // of a one-wave block).
+  const int n = N - 2;
   for (int comp = (threadIdx.x >> 6); comp < 2 && (threadIdx.x & 63) == 0;
        comp += (blockDim.x >= 128 ? 2 : 1)) {
-    const int n = N - 2;
     double prev = 0.0;
 #pragma unroll 8
     for (int i = 0; i < n; ++i) {
@@ -639,17 +639,23 @@ __global__ __launch_bounds__(512) void k_group_sum(const Segment* __restrict__ s
 // K4: one block per job: sum the group records in order and run the FP64 finish.
 constexpr int kMaxRecord = 8 * (kMaxKnots - 1) + 1 + 6 * kMaxRes;
 
-__global__ __launch_bounds__(256) void k_job_finish(const Job* __restrict__ jobs, ArgTable targ,
-                                                     unsigned long long seq, double* out_override) {
+constexpr int kMaxConsts = 3 * kMaxKnots - 5;
+constexpr int kFinishThreads = 256;
+
+// One block of kFinishThreads per job.  `jobs` == nullptr: a single job passed by value in `one`
+// (saves the dependent load of its descriptor).
+__global__ __launch_bounds__(kFinishThreads) void k_job_finish(const Job* __restrict__ jobs, Job one, ArgTable targ,
+                                                              unsigned long long seq, double* out_override) {
   __shared__ double fin[2 * kMaxRecord];
-  __shared__ double kc[3 * kMaxKnots];
-  const Job jb = jobs[blockIdx.x];
+  __shared__ double kc[kMaxConsts];
+  const Job jb = jobs ? jobs[blockIdx.x] : one;
   const int rs = jb.rs, nf = 2 * rs, nkc = 3 * jb.N - 5;
-  // the Thomas factors are requested first; they are only needed once the records are summed
-  double kcv[2];
+  // the constants are requested first; they are only needed once the records are summed
+  constexpr int KPT = (kMaxConsts + kFinishThreads - 1) / kFinishThreads;
+  double kcv[KPT];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int i = threadIdx.x + j * blockDim.x;
+  for (int j = 0; j < KPT; ++j) {
+    const int i = threadIdx.x + j * kFinishThreads;
     kcv[j] = i < nkc ? jb.consts[i] : 0.0;
   }
   // field f < rs of the data groups, then of the normalisation groups.  Each thread takes up to FPT
@@ -685,8 +691,8 @@ __global__ __launch_bounds__(256) void k_job_finish(const Job* __restrict__ jobs
       if (f0 + j * blockDim.x < nf) fin[f0 + j * blockDim.x] = sum[j];
   }
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int i = threadIdx.x + j * blockDim.x;
+  for (int j = 0; j < KPT; ++j) {
+    const int i = threadIdx.x + j * kFinishThreads;
     if (i < nkc) kc[i] = kcv[j];
   }
   __syncthreads();
@@ -1014,13 +1020,16 @@ hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const in
 
 hipError_t launch_reduce(const Segment* segs, const Job* jobs, const int2* tasks, int n_tasks, int n_jobs,
                          const ArgTable* targ, hipStream_t st,
-                         unsigned long long seq, double* out_override) {
+                         unsigned long long seq, double* out_override, const Job* single) {
   (void)hipGetLastError();
   static const ArgTable empty{};
   k_group_sum<<<n_tasks, 512, 0, st>>>(segs, jobs, tasks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_job_finish<<<n_jobs, 256, 0, st>>>(jobs, targ ? *targ : empty, seq, out_override);
+  static const Job none{};
+  if (single && n_jobs != 1) return hipErrorInvalidValue;
+  k_job_finish<<<n_jobs, kFinishThreads, 0, st>>>(single ? nullptr : jobs, single ? *single : none,
+                                                  targ ? *targ : empty, seq, out_override);
   return hipGetLastError();
 }
 

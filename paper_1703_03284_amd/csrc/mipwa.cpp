@@ -119,6 +119,8 @@ int mipwa_ctx::rebuild_launch() {
   jb[1].out = d_out.as<double>();
   jb[1].seq_out = nullptr;
   HIPCHK(hipMemcpy(d_job.p, jb, sizeof(jb), hipMemcpyHostToDevice), "job upload");
+  h_jobs[0] = jb[0];
+  h_jobs[1] = jb[1];
   launch_dirty = false;
   return MIPWA_OK;
 }
@@ -177,12 +179,8 @@ int mipwa_ctx::ensure_cache(hipStream_t st) {
 
 int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigned long long s, double* out) {
   mipwa_ctx* ctx = this;
-  if (timed) {
-    // the events are about to be recorded again: take the previous timed evaluation's times first
-    int rc = fold_timing();
-    if (rc) return rc;
-    HIPCHK(hipEventRecord(ev_t0, st), "event");
-  }
+  const int cs = ev_cur;
+  if (timed) HIPCHK(hipEventRecord(ev_t[cs][0], st), "event");
   if (!use_arg) {
     HIPCHK(launch_upload(d_blob.p, h_blob.dev, upload16(), st), "parameter upload");
     HIPCHK(hipEventRecord(ev_staged, st), "event");
@@ -190,12 +188,19 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigne
   // with use_arg the table and theta travel in the kernel arguments (copied at the launch)
   HIPCHK(launch_eval(fp64, mh.R, otf, d_segs.as<Segment>(), d_block_seg.as<int2>(), d_job.as<Job>() + (to_host ? 0 : 1),
                      n_blocks, waves_eff, mh.N - 1, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32,
-                     use_arg ? &h_args : nullptr, st, timed ? ev_t1 : nullptr, timed ? ev_t2 : nullptr),
+                     use_arg ? &h_args : nullptr, st, timed ? ev_t[cs][1] : nullptr, timed ? ev_t[cs][2] : nullptr),
          "likelihood kernel");
   HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), d_tasks.as<int2>(), n_tasks, 1,
-                       use_arg ? &h_args : nullptr, st, s, out),
+                       use_arg ? &h_args : nullptr, st, s, out, &h_jobs[to_host ? 0 : 1]),
          "reduction kernels");
-  if (timed) HIPCHK(hipEventRecord(ev_t3, st), "event");
+  if (timed) {
+    HIPCHK(hipEventRecord(ev_t[cs][3], st), "event");
+    ev_last = cs;
+    ev_cur = cs ^ 1;
+    // the other set holds the previous timed evaluation: take its times now that this one is queued
+    int rc = fold_timing(cs ^ 1);
+    if (rc) return rc;
+  }
   return MIPWA_OK;
 }
 
@@ -234,18 +239,25 @@ int mipwa_ctx::wait_result(unsigned long long s) {
   }
 }
 
-int mipwa_ctx::fold_timing() {
+int mipwa_ctx::fold_timing(int set) {
   mipwa_ctx* ctx = this;
-  if (!timing_unread) return MIPWA_OK;
-  timing_unread = false;
-  HIPCHK(hipEventSynchronize(ev_t3), "event sync");
+  if (!set_unread[set]) return MIPWA_OK;
+  set_unread[set] = false;
+  HIPCHK(hipEventSynchronize(ev_t[set][3]), "event sync");
   float a = 0, b = 0;
-  if (hipEventElapsedTime(&a, ev_t0, ev_t3) == hipSuccess && hipEventElapsedTime(&b, ev_t1, ev_t2) == hipSuccess) {
+  if (hipEventElapsedTime(&a, ev_t[set][0], ev_t[set][3]) == hipSuccess &&
+      hipEventElapsedTime(&b, ev_t[set][1], ev_t[set][2]) == hipSuccess) {
     t_count += 1;
     t_total += a;
     t_stream += b;
   }
   (void)hipGetLastError();
+  return MIPWA_OK;
+}
+
+int mipwa_ctx::fold_all_timing() {
+  for (int k = 0; k < 2; ++k)
+    if (int rc = fold_timing(ev_cur ^ 1 ^ k)) return rc;
   return MIPWA_OK;
 }
 
@@ -259,7 +271,7 @@ int mipwa_ctx::run_sync_eval() {
   if (rc) return rc;
   rc = wait_result(s);
   if (rc) return rc;
-  if (timing_on) timing_unread = timing_pending = true;
+  if (timing_on) set_unread[ev_last] = timing_pending = true;
   return MIPWA_OK;
 }
 
@@ -303,11 +315,13 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
     delete ctx;
     return MIPWA_E_HIP;
   }
-  for (hipEvent_t* e : {&ctx->ev_staged, &ctx->ev_t0, &ctx->ev_t1, &ctx->ev_t2, &ctx->ev_t3})
-    if (hipEventCreate(e) != hipSuccess) {
-      delete ctx;
-      return MIPWA_E_HIP;
-    }
+  bool events_ok = hipEventCreate(&ctx->ev_staged) == hipSuccess;
+  for (auto& set : ctx->ev_t)
+    for (hipEvent_t& e : set) events_ok = events_ok && hipEventCreate(&e) == hipSuccess;
+  if (!events_ok) {
+    delete ctx;
+    return MIPWA_E_HIP;
+  }
   const mipwa::ModelHost& mh = ctx->mh;
   const size_t real = ctx->fp64 ? 8 : 4;
   const size_t tbytes = table_words(mh.N - 1, mh.R) * real;
@@ -316,7 +330,7 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
   ctx->consts_off = ctx->upload16();  // the per-evaluation upload never reaches the constants
   ctx->arg_theta_off = (int)((tbytes + 7) / 8 * 8);
   ctx->use_arg = ctx->arg_theta_off + mh.P * sizeof(double) <= (size_t)kArgBytes;
-  const size_t blob = ctx->consts_off + 3 * (size_t)mh.N * sizeof(double);
+  const size_t blob = ctx->consts_off + (size_t)consts_words(mh.N) * sizeof(double);
   if (ctx->d_blob.alloc(blob) != hipSuccess || ctx->h_blob.alloc(ctx->upload16(), true) != hipSuccess ||
       ctx->d_out.alloc((1 + mh.P) * sizeof(double)) != hipSuccess ||
       ctx->h_out.alloc((2 + mh.P) * sizeof(double), true) != hipSuccess ||
@@ -328,7 +342,7 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
   std::memset(ctx->h_out.p, 0, (2 + mh.P) * sizeof(double));
   // constant part of the FP64 table (at consts_off): Thomas factors of the interior spline system, h
   const int ni = mh.N - 2;
-  std::vector<double> cst(2 * (size_t)ni + mh.N - 1);
+  std::vector<double> cst(consts_words(mh.N));
   for (int i = 0; i < ni; ++i) {
     cst[i] = mh.th_c[i];
     cst[ni + i] = 1.0 / mh.th_d[i];
@@ -460,10 +474,11 @@ int mipwa_last_timing(const mipwa_ctx* cctx, double* total_ms, double* stream_ms
   mipwa_ctx* ctx = const_cast<mipwa_ctx*>(cctx);
   if (!ctx) return MIPWA_E_INVAL;
   if (!ctx->timing_pending) return ctx->fail(MIPWA_E_STATE, "no evaluation timed yet");
-  HIPCHK(hipEventSynchronize(ctx->ev_t3), "event sync");
+  const int set = ctx->ev_last;
+  HIPCHK(hipEventSynchronize(ctx->ev_t[set][3]), "event sync");
   float a = 0, b = 0;
-  HIPCHK(hipEventElapsedTime(&a, ctx->ev_t0, ctx->ev_t3), "event time");
-  HIPCHK(hipEventElapsedTime(&b, ctx->ev_t1, ctx->ev_t2), "event time");
+  HIPCHK(hipEventElapsedTime(&a, ctx->ev_t[set][0], ctx->ev_t[set][3]), "event time");
+  HIPCHK(hipEventElapsedTime(&b, ctx->ev_t[set][1], ctx->ev_t[set][2]), "event time");
   if (total_ms) *total_ms = a;
   if (stream_ms) *stream_ms = b;
   return MIPWA_OK;
@@ -472,7 +487,7 @@ int mipwa_last_timing(const mipwa_ctx* cctx, double* total_ms, double* stream_ms
 int mipwa_set_timing(mipwa_ctx* ctx, int on) {
   if (!ctx) return MIPWA_E_INVAL;
   ctx->timing_on = on != 0;
-  ctx->timing_unread = false;
+  ctx->set_unread[0] = ctx->set_unread[1] = false;
   ctx->t_count = 0;
   ctx->t_total = ctx->t_stream = 0.0;
   return MIPWA_OK;
@@ -480,7 +495,7 @@ int mipwa_set_timing(mipwa_ctx* ctx, int on) {
 
 int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_ms, double* mean_stream_ms) {
   if (!ctx) return MIPWA_E_INVAL;
-  if (int rc = const_cast<mipwa_ctx*>(ctx)->fold_timing()) return rc;
+  if (int rc = const_cast<mipwa_ctx*>(ctx)->fold_all_timing()) return rc;
   const double n = ctx->t_count > 0 ? (double)ctx->t_count : 1.0;
   if (count) *count = ctx->t_count;
   if (mean_total_ms) *mean_total_ms = ctx->t_total / n;

@@ -286,7 +286,7 @@ static void serve_worker(mipwa_server* S, SJob* J) {
     J->G_n = n_groups(ns->nb);
     J->rs = record_size(J->mh.N - 1, J->mh.R, false);
     const int ni = J->mh.N - 2;
-    std::vector<double> cst(2 * (size_t)ni + J->mh.N - 1);
+    std::vector<double> cst(consts_words(J->mh.N));
     for (int i = 0; i < ni; ++i) {
       cst[i] = J->mh.th_c[i];
       cst[ni + i] = 1.0 / J->mh.th_d[i];
