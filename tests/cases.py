@@ -35,6 +35,15 @@ class Problem:
         th = self.theta if theta is None else theta
         return L.nll_and_grad(self.model, th, self.events, self.oracle_norm(), self.log_eps_sum, shapes=shapes)
 
+    def nll_scale(self, theta=None):
+        """2 sum_i |ln|A_i|^2| + 2 n |ln I|: the size of the terms whose sum is -2 ln L.  Rounding in the
+        working precision is relative to this, not to -2 ln L itself, which can cancel to near zero."""
+        th = self.theta if theta is None else theta
+        a = L.amplitude(self.model, th, *self.events)
+        I = L.norm_integral(self.model, th, self.oracle_norm())
+        n = len(self.events[0])
+        return 2.0 * float(np.sum(np.abs(np.log(a.real ** 2 + a.imag ** 2)))) + 2.0 * n * abs(np.log(I))
+
     def context(self, precision, table_mode=False):
         from paper_1703_03284_amd import context_for
         ctx = context_for(self.workload.decay, self.knots, self.workload.resonances, precision)
@@ -72,6 +81,13 @@ def make_problem(workload, n_events, n_norm, seed=0, knots=None, eff="auto", the
         th = synth.perturb_theta(synth.truth_theta(len(kn), workload.resonances, workload.seed("truth")),
                                  len(kn), workload.n_res, workload.seed("start"))
     return Problem(workload, m, kn, th, ev, e_ev, (s12, s13, w), e_nm, table)
+
+
+def with_grid_norm(prob: Problem, spacing: float) -> Problem:
+    """The same problem normalised on the evenly spaced grid of the given spacing (Sec. 4), flat
+    efficiency."""
+    g = synth.grid_points(prob.workload.decay, spacing)
+    return Problem(prob.workload, prob.model, prob.knots, prob.theta, prob.events, None, g, None, None)
 
 
 def rel(a, b):
