@@ -17,8 +17,9 @@
  *
  * Conventions
  *   Units: GeV, GeV^2, GeV^-1.  Particle 1 is the h-, particles 2 and 3 the identical h+ (m2 == m3).
- *   Parameter vector theta (P = 2N + 4R doubles):
+ *   Parameter vector theta (P = 2N + 4R doubles, default polar S-wave form):
  *     [a_0, phi_0, ..., a_{N-1}, phi_{N-1},  |c_1|, arg c_1, ..., |c_R|, arg c_R,  m_1, G_1, ..., m_R, G_R]
+ *   (mipwa_set_swave_form selects the Cartesian knot form or the isobar S-wave.)
  *   The S-wave is component 0 of Eq. 1 with coefficient 1.
  *   Every function returns an int status: MIPWA_OK (0) or a negative MIPWA_E_* code; no C++ exception
  *   crosses the ABI.  On error, mipwa_last_error(ctx) holds a message.
@@ -64,7 +65,9 @@ typedef struct {
 } mipwa_res;
 
 /* Decay kinematics, D barrier radius rD >= 0, the N strictly increasing knot positions in m^2(h+h-)
- * (Sec. 2 boundary points; 3 <= N <= MIPWA_MAX_KNOTS) and R <= MIPWA_MAX_RES resonances. */
+ * (Sec. 2 boundary points; 2 <= N <= MIPWA_MAX_KNOTS; two knots give a straight-line S-wave, the
+ * carrier of the isobar form below) and R <= MIPWA_MAX_RES resonances (spin 0 entries are the scalar
+ * Breit-Wigners of an isobar S-wave). */
 typedef struct {
   double M, m1, m2, m3, rD;
   int n_knots;
@@ -84,7 +87,22 @@ void mipwa_destroy(mipwa_ctx* ctx);
 /* Message for the last failed call on ctx (never NULL; empty if none).  Valid until the next call. */
 const char* mipwa_last_error(const mipwa_ctx* ctx);
 const char* mipwa_strerror(int status);
+/* Number of parameters P of the current S-wave form (2N + 4R, or 2 + 4R for the isobar form). */
 int mipwa_n_params(const mipwa_ctx* ctx);
+
+/* S-wave parameter form, which sets the layout of theta, the fixed mask and the gradient:
+ *   MIPWA_SWAVE_POLAR (default): the knots as (a_k, phi_k), z_k = a_k e^{i phi_k} (Sec. 2);
+ *   MIPWA_SWAVE_CARTESIAN: the knots as (Re z_k, Im z_k), the alternative the paper's abstract names
+ *     in its source text; same model, the knot partials are dL/dRe z_k, dL/dIm z_k;
+ *   MIPWA_SWAVE_ISOBAR: the S-wave of the isobar model (Sec. 2): one constant non-resonant term
+ *     c_NR = |c_NR| e^{i arg c_NR}, entering A once, plus the model's spin-0 resonances as scalar
+ *     Breit-Wigners; theta = [|c_NR|, arg c_NR, (|c_r|, arg c_r)_r, (m_r, Gamma_r)_r].  The model must
+ *     have exactly two knots (they carry c_NR / 2 each).
+ * Resets the parameters (set them again) and the fixed mask (masses and widths fixed).  Not available
+ * in the serving API, whose jobs use the polar form.  Errors: E_INVAL (unknown form; isobar with
+ * N != 2). */
+enum { MIPWA_SWAVE_POLAR = 0, MIPWA_SWAVE_CARTESIAN = 1, MIPWA_SWAVE_ISOBAR = 2 };
+int mipwa_set_swave_form(mipwa_ctx* ctx, int form);
 
 /* Data events (the sample whose likelihood is maximised, Sec. 2).  s12[i], s13[i] are host arrays of n
  * doubles, each event inside the Dalitz region to within 1e-9 (M - m3)^2.  eff (nullable) gives the

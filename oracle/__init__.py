@@ -13,7 +13,9 @@ massively-parallel fitting framework" (Sun, Aoude, dos Reis, Sokoloff):
   cubic-spline interpolation in the complex plane between knots;
 * Sec. 4 -- Bose symmetrisation over the two m^2(h+h-) axes;
 * Sec. 2 and Sec. 4 -- the unbinned maximum-likelihood fit with the normalisation integral
-  recomputed every iteration from points spread over the Dalitz plane.
+  recomputed every iteration from points spread over the Dalitz plane;
+* Sec. 2 -- the isobar S-wave (a constant non-resonant term plus scalar Breit-Wigners) and, as the
+  abstract's source text names it, the knots as real and imaginary parts (module forms).
 
 The paper leaves the spline boundary conditions, the Breit-Wigner form, barrier factors and angular
 terms to references it does not reproduce.  The readings used here (natural spline on Re and Im,
@@ -25,4 +27,4 @@ forms, library special cases, brute force or invariants.  Absolute agreement wit
 fitted values cannot be checked (the paper prints none), so that comparison is parity unpinned.
 """
 from .model import Model, Res  # noqa: F401
-from . import kinematics, spline, resonance, likelihood, fit, philox, generate  # noqa: F401
+from . import kinematics, spline, resonance, likelihood, fit, philox, generate, forms  # noqa: F401

@@ -15,10 +15,12 @@ from scipy.optimize import minimize
 from .likelihood import nll_and_grad
 
 
-def canonical(model, theta):
-    """Fold each (magnitude, phase) pair to magnitude >= 0 and phase in (-pi, pi]."""
+def canonical(model, theta, n_pairs=None):
+    """Fold each (magnitude, phase) pair to magnitude >= 0 and phase in (-pi, pi]: the first n_pairs
+    pairs of theta (default: the N knots and R coefficients of the polar spline layout)."""
     th = np.array(theta, dtype=np.float64, copy=True)
-    n_pairs = model.n_knots + model.n_res
+    if n_pairs is None:
+        n_pairs = model.n_knots + model.n_res
     for k in range(n_pairs):
         a, p = th[2 * k], th[2 * k + 1]
         if a < 0:
@@ -40,16 +42,22 @@ def hessian(func_grad, x, step_rel=1e-4):
     return 0.5 * (H + H.T)
 
 
-def fit(model, theta0, events, norm, fixed, log_eps_sum=0.0, gtol=1e-5, maxiter=5000):
+def fit(model, theta0, events, norm, fixed, log_eps_sum=0.0, gtol=1e-5, maxiter=5000, objective=None,
+        n_pairs=None):
+    """objective(model, theta, events, norm, log_eps_sum, shapes) -> (-2 ln L, gradient), default the
+    polar spline form; n_pairs leading (magnitude, phase) pairs precede the masses and widths."""
     theta0 = np.asarray(theta0, dtype=np.float64)
     fixed = np.asarray(fixed, dtype=bool)
     free = np.flatnonzero(~fixed)
-    shapes = bool((~fixed[2 * model.n_knots + 2 * model.n_res:]).any())
+    objective = objective or nll_and_grad
+    if n_pairs is None:
+        n_pairs = model.n_knots + model.n_res
+    shapes = bool((~fixed[2 * n_pairs:]).any())
 
     def fg(x):
         th = theta0.copy()
         th[free] = x
-        v, g = nll_and_grad(model, th, events, norm, log_eps_sum, shapes=shapes)
+        v, g = objective(model, th, events, norm, log_eps_sum, shapes=shapes)
         return v, g[free]
 
     res = minimize(fg, theta0[free], jac=True, method="BFGS",
@@ -64,7 +72,7 @@ def fit(model, theta0, events, norm, fixed, log_eps_sum=0.0, gtol=1e-5, maxiter=
     cov = np.zeros((len(theta0), len(theta0)))
     cov[np.ix_(free, free)] = V
     return {
-        "theta": canonical(model, th),
+        "theta": canonical(model, th, n_pairs),
         "theta_raw": th,
         "nll": v,
         "edm": 0.5 * float(g @ Hinv @ g),

@@ -16,6 +16,7 @@ from . import _lib as L
 __all__ = ["Context", "Server", "MipwaError", "Resonance", "FitResult", "FP64", "MIXED", "context_for"]
 
 FP64, MIXED = L.MIPWA_FP64, L.MIPWA_MIXED
+SWAVE_POLAR, SWAVE_CARTESIAN, SWAVE_ISOBAR = 0, 1, 2
 
 
 class MipwaError(RuntimeError):
@@ -120,6 +121,12 @@ class Context:
         nx, ny = t.shape
         self._check(self._lib.mipwa_set_eff_table(self._h, t.ctypes.data_as(C.POINTER(C.c_float)), nx, ny,
                                                   float(lo), float(hi)), "set_eff_table")
+
+    def set_swave_form(self, form):
+        """SWAVE_POLAR (default), SWAVE_CARTESIAN or SWAVE_ISOBAR (two-knot model); resets theta and
+        the fixed mask, and changes n_params."""
+        self._check(self._lib.mipwa_set_swave_form(self._h, int(form)), "set_swave_form")
+        self.n_params = self._lib.mipwa_n_params(self._h)
 
     def set_fixed(self, fixed):
         f = np.ascontiguousarray(fixed, dtype=np.uint8)

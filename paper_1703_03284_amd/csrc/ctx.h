@@ -17,9 +17,10 @@ struct mipwa_ctx {
   mipwa::PointSet ev, nm;
   mipwa::EffTable eff;
 
-  std::vector<double> theta;
+  std::vector<double> theta;       // internal: the polar spline layout (2N + 4R)
   bool have_theta = false;
-  std::vector<unsigned char> fixed;
+  std::vector<unsigned char> fixed;  // external layout (ext_P entries)
+  int swave = mipwa::kSwavePolar;    // parameter form seen through the C ABI
   bool otf = false;
 
   std::vector<double> cache_shape;
@@ -69,6 +70,11 @@ struct mipwa_ctx {
   }
 
   int fail(int code, const std::string& msg);
+  // external parameter count and the offset of the resonance coefficients in the external layout
+  int ext_P() const { return swave == mipwa::kSwaveIsobar ? 2 + 4 * mh.R : mh.P; }
+  int ext_res_off() const { return swave == mipwa::kSwaveIsobar ? 2 : 2 * mh.N; }
+  // external theta -> internal (polar spline) theta
+  void to_internal(const double* ext, double* internal) const;
   int rebuild_launch();
   int stage_params();
   bool shapes_changed() const;

@@ -18,6 +18,9 @@ constexpr int kTile = MIPWA_TILE;
 static_assert(kTile % 64 == 0, "tiles hold whole wavefronts");
 constexpr int kMaxWaves = 16;
 constexpr int kMaxRes = 4;
+// S-wave parameter forms (mipwa_set_swave_form).  Inside the library theta is always the polar
+// spline form; these select how the finish writes the gradient.
+constexpr int kSwavePolar = 0, kSwaveCartesian = 1, kSwaveIsobar = 2;
 constexpr int kMaxKnots = 128;
 // Doubles of the per-model constants: Thomas factors and interval widths.
 __host__ __device__ inline int consts_words(int N) { return 3 * N - 5; }
@@ -79,7 +82,7 @@ struct Job {
   int G_d, G_n;
   int N, R, rs, otf;
   int theta_off;         // byte offset of theta in the launch's ArgTable when tab64 == nullptr
-  int pad;
+  int swave;             // parameter form of the S-wave (kSwave*): the layout of the gradient written
 };
 
 __host__ __device__ inline int n_groups(int n_blocks) { return (n_blocks + kGroup - 1) / kGroup; }

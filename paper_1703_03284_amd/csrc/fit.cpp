@@ -191,7 +191,8 @@ bool cholesky_inverse(std::vector<double> A, size_t n, std::vector<double>& inv)
 
 }  // namespace
 
-int bfgs_fit(const FullEval& fg, int P, int N, int R, const std::vector<unsigned char>& fixed, const double* theta0,
+int bfgs_fit(const FullEval& fg, int P, const std::vector<int>& polar_pairs, const std::vector<unsigned char>& fixed,
+             const double* theta0,
              double tol, int max_iter, bool want_hess, double eps_rel, FitOut& out) {
   Objective obj{&fg, {}, std::vector<double>(theta0, theta0 + P), std::vector<double>(P), 0};
   for (int p = 0; p < P; ++p)
@@ -308,19 +309,19 @@ int bfgs_fit(const FullEval& fg, int P, int N, int R, const std::vector<unsigned
     for (size_t j = 0; j < n; ++j) out.cov[(size_t)obj.free[i] * P + obj.free[j]] = V[i * n + j];
   // fold (magnitude, phase) pairs: magnitude >= 0, phase in (-pi, pi]; a sign flip of a magnitude flips
   // its covariance row and column
-  for (int k = 0; k < N + R; ++k) {
-    double a = out.theta[2 * k], p = out.theta[2 * k + 1];
+  for (const int i : polar_pairs) {
+    double a = out.theta[i], p = out.theta[i + 1];
     if (a < 0) {
       a = -a;
       p += M_PI;
       for (int q = 0; q < P; ++q) {
-        out.cov[(size_t)(2 * k) * P + q] = -out.cov[(size_t)(2 * k) * P + q];
-        out.cov[(size_t)q * P + 2 * k] = -out.cov[(size_t)q * P + 2 * k];
+        out.cov[(size_t)i * P + q] = -out.cov[(size_t)i * P + q];
+        out.cov[(size_t)q * P + i] = -out.cov[(size_t)q * P + i];
       }
     }
     p = M_PI - std::fmod(std::fmod(M_PI - p, 2.0 * M_PI) + 2.0 * M_PI, 2.0 * M_PI);
-    out.theta[2 * k] = a;
-    out.theta[2 * k + 1] = p;
+    out.theta[i] = a;
+    out.theta[i + 1] = p;
   }
   out.nll = f;
   out.edm = edm;
@@ -337,7 +338,7 @@ extern "C" int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* the
   using namespace mipwa;
   if (!ctx) return MIPWA_E_INVAL;
   if (!theta_inout) return ctx->fail(MIPWA_E_INVAL, "theta is NULL");
-  const int P = ctx->mh.P;
+  const int P = ctx->ext_P();
   const double tol = opts && opts->tol_edm > 0 ? opts->tol_edm : 1e-6;
   const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 1000;
   const bool want_hess = opts ? opts->hessian != 0 : true;
@@ -358,7 +359,13 @@ extern "C" int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* the
   // FP32 streams leave ~1e-11 relative noise in f; allow it in the sufficient-decrease test
   const double eps_rel = ctx->fp64 ? 1e-13 : 1e-10;
   FitOut out;
-  int rc = bfgs_fit(fg, P, ctx->mh.N, ctx->mh.R, ctx->fixed, theta_inout, tol, max_iter, want_hess, eps_rel, out);
+  // (magnitude, phase) pairs of the external layout: the polar knots, c_NR of the isobar form, the c_r
+  std::vector<int> pairs;
+  if (ctx->swave == kSwavePolar)
+    for (int k = 0; k < ctx->mh.N; ++k) pairs.push_back(2 * k);
+  if (ctx->swave == kSwaveIsobar) pairs.push_back(0);
+  for (int r = 0; r < ctx->mh.R; ++r) pairs.push_back(ctx->ext_res_off() + 2 * r);
+  int rc = bfgs_fit(fg, P, pairs, ctx->fixed, theta_inout, tol, max_iter, want_hess, eps_rel, out);
   if (rc) return ctx->fail(rc, out.err.empty() ? std::string(ctx->err) : out.err);
   std::copy(out.theta.begin(), out.theta.end(), theta_inout);
   (void)mipwa_set_params(ctx, theta_inout, P);

@@ -21,9 +21,12 @@ struct GenState {
   GenArgs g{};
 };
 
-int gen_setup(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t seed, double fmax, int mode, GenState& s) {
+int gen_setup(mipwa_ctx* ctx, const double* ext_theta, int n_theta, uint64_t seed, double fmax, int mode, GenState& s) {
   const ModelHost& mh = ctx->mh;
-  if (!theta || n_theta != mh.P) return ctx->fail(MIPWA_E_INVAL, "theta must have P entries");
+  if (!ext_theta || n_theta != ctx->ext_P()) return ctx->fail(MIPWA_E_INVAL, "theta must have P entries");
+  std::vector<double> internal(mh.P);
+  ctx->to_internal(ext_theta, internal.data());
+  const double* theta = internal.data();
   int rc = mh.check_theta(theta, ctx->err);
   if (rc) return rc;
   const int nint = mh.N - 1;

@@ -63,8 +63,8 @@ int ModelHost::init(const mipwa_model* m, std::string& err) {
     err = "rD must be >= 0";
     return MIPWA_E_INVAL;
   }
-  if (m->n_knots < 3 || m->n_knots > MIPWA_MAX_KNOTS || !m->knots) {
-    os << "n_knots must be in [3, " << MIPWA_MAX_KNOTS << "]";
+  if (m->n_knots < 2 || m->n_knots > MIPWA_MAX_KNOTS || !m->knots) {
+    os << "n_knots must be in [2, " << MIPWA_MAX_KNOTS << "]";
     err = os.str();
     return MIPWA_E_INVAL;
   }

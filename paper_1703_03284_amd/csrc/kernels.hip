@@ -529,20 +529,44 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
       yr += d * u[2 * (k - 1)];
       yi += d * u[2 * (k - 1) + 1];
     }
-    const double a = th[2 * k], ph = th[2 * k + 1];
-    double sn, cs;
-    sincos(ph, &sn, &cs);
-    out[1 + 2 * k] = yr * cs + yi * sn;
-    out[2 + 2 * k] = a * (-yr * sn + yi * cs);
+    if (jb.swave == kSwavePolar) {
+      const double a = th[2 * k], ph = th[2 * k + 1];
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      out[1 + 2 * k] = yr * cs + yi * sn;
+      out[2 + 2 * k] = a * (-yr * sn + yi * cs);
+    } else if (jb.swave == kSwaveCartesian) {
+      out[1 + 2 * k] = yr;
+      out[2 + 2 * k] = yi;
+    } else {
+      gy[2 * k] = yr;  // isobar: combined below
+      gy[2 * k + 1] = yi;
+    }
   }
+  // Isobar S-wave: a constant c_NR, carried as a two-knot spline with both knots at c_NR / 2 (which
+  // the symmetrised sum S(s12) + S(s13) returns as c_NR).  Its partials are the two knots' z-partials
+  // Y = y_0 + y_1 taken through z = c_NR / 2 to (|c_NR|, arg c_NR).
+  if (jb.swave == kSwaveIsobar) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double yr = gy[0] + gy[2], yi = gy[1] + gy[3];
+      const double cm = 2.0 * th[0], ph = th[1];
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      out[1] = 0.5 * (yr * cs + yi * sn);
+      out[2] = 0.5 * cm * (-yr * sn + yi * cs);
+    }
+  }
+  // external offset of the resonance block: after the knots, or after c_NR
+  const int o = jb.swave == kSwaveIsobar ? 2 : 2 * N;
   for (int r = threadIdx.x; r < R; r += blockDim.x) {
     const double gr = fd[s0 + 1 + 2 * r] + scale * fn[s0 + 1 + 2 * r];
     const double gi = fd[s0 + 2 + 2 * r] + scale * fn[s0 + 2 + 2 * r];
     const double cm = th[2 * N + 2 * r], ca = th[2 * N + 2 * r + 1];
     double sn, cs;
     sincos(ca, &sn, &cs);
-    out[1 + 2 * N + 2 * r] = gr * cs + gi * sn;
-    out[2 + 2 * N + 2 * r] = cm * (-gr * sn + gi * cs);
+    out[1 + o + 2 * r] = gr * cs + gi * sn;
+    out[2 + o + 2 * r] = cm * (-gr * sn + gi * cs);
     double dm = 0.0, dg = 0.0;
     if (jb.otf) {
       const int om = s0 + 1 + 2 * R + 2 * r, og = s0 + 1 + 4 * R + 2 * r;
@@ -552,8 +576,8 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
       dm = cr * hmr + ci * hmi;
       dg = cr * hgr + ci * hgi;
     }
-    out[1 + 2 * N + 2 * R + 2 * r] = dm;
-    out[2 + 2 * N + 2 * R + 2 * r] = dg;
+    out[1 + o + 2 * R + 2 * r] = dm;
+    out[2 + o + 2 * R + 2 * r] = dg;
   }
   if (threadIdx.x == 0) out[0] = -2.0 * fd[s0] + jb.c_eps + 2.0 * jb.n_ev * log(I);
   __threadfence_system();

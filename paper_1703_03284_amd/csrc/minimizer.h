@@ -19,7 +19,9 @@ struct FitOut {
   std::string err;
 };
 
-int bfgs_fit(const FullEval& fg, int P, int N, int R, const std::vector<unsigned char>& fixed,
+// polar_pairs: indices i of (magnitude, phase) pairs (theta[i], theta[i+1]) folded to magnitude >= 0,
+// phase in (-pi, pi] at the end
+int bfgs_fit(const FullEval& fg, int P, const std::vector<int>& polar_pairs, const std::vector<unsigned char>& fixed,
              const double* theta0, double tol, int max_iter, bool hessian, double eps_rel, FitOut& out);
 
 }  // namespace mipwa

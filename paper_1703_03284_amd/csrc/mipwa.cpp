@@ -40,6 +40,24 @@ int default_blocks(int device) {
 
 }  // namespace
 
+void mipwa_ctx::to_internal(const double* ext, double* in) const {
+  const int N = mh.N, R = mh.R;
+  if (swave == kSwaveCartesian) {
+    for (int k = 0; k < N; ++k) {
+      in[2 * k] = std::hypot(ext[2 * k], ext[2 * k + 1]);
+      in[2 * k + 1] = std::atan2(ext[2 * k + 1], ext[2 * k]);
+    }
+    std::copy(ext + 2 * N, ext + mh.P, in + 2 * N);
+  } else if (swave == kSwaveIsobar) {
+    // c_NR carried by both knots of a two-knot spline at c_NR / 2
+    in[0] = in[2] = 0.5 * ext[0];
+    in[1] = in[3] = ext[1];
+    std::copy(ext + 2, ext + 2 + 4 * R, in + 4);
+  } else {
+    std::copy(ext, ext + mh.P, in);
+  }
+}
+
 // Sequence numbers of synchronous evaluations, unique in the process.
 static std::atomic<unsigned long long> g_eval_seq{0};
 
@@ -113,6 +131,7 @@ int mipwa_ctx::rebuild_launch() {
     jb[k].R = mh.R;
     jb[k].rs = rs;
     jb[k].otf = otf ? 1 : 0;
+    jb[k].swave = swave;
   }
   jb[0].out = h_out_dev;
   jb[0].seq_out = reinterpret_cast<unsigned long long*>(h_out_dev + 1 + mh.P);
@@ -370,7 +389,23 @@ void mipwa_destroy(mipwa_ctx* ctx) {
 
 const char* mipwa_last_error(const mipwa_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
 
-int mipwa_n_params(const mipwa_ctx* ctx) { return ctx ? ctx->mh.P : MIPWA_E_INVAL; }
+int mipwa_n_params(const mipwa_ctx* ctx) { return ctx ? ctx->ext_P() : MIPWA_E_INVAL; }
+
+int mipwa_set_swave_form(mipwa_ctx* ctx, int form) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (form != MIPWA_SWAVE_POLAR && form != MIPWA_SWAVE_CARTESIAN && form != MIPWA_SWAVE_ISOBAR)
+    return ctx->fail(MIPWA_E_INVAL, "unknown S-wave form");
+  if (form == MIPWA_SWAVE_ISOBAR && ctx->mh.N != 2)
+    return ctx->fail(MIPWA_E_INVAL, "the isobar form needs a model with exactly two knots");
+  ctx->swave = form;
+  ctx->have_theta = false;
+  const int P = ctx->ext_P(), o = ctx->ext_res_off() + 2 * ctx->mh.R;
+  ctx->fixed.assign(P, 0);
+  for (int p = o; p < P; ++p) ctx->fixed[p] = 1;
+  ctx->otf = false;
+  ctx->launch_dirty = true;
+  return MIPWA_OK;
+}
 
 int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves) {
   if (!ctx) return MIPWA_E_INVAL;
@@ -421,10 +456,10 @@ int mipwa_load_norm(mipwa_ctx* ctx, const double* s12, const double* s13, const 
 
 int mipwa_set_fixed(mipwa_ctx* ctx, const unsigned char* fixed, int n) {
   if (!ctx) return MIPWA_E_INVAL;
-  if (!fixed || n != ctx->mh.P) return ctx->fail(MIPWA_E_INVAL, "fixed mask must have P entries");
+  if (!fixed || n != ctx->ext_P()) return ctx->fail(MIPWA_E_INVAL, "fixed mask must have P entries");
   ctx->fixed.assign(fixed, fixed + n);
   bool otf = false;
-  for (int p = 2 * ctx->mh.N + 2 * ctx->mh.R; p < ctx->mh.P; ++p) otf |= fixed[p] == 0;
+  for (int p = ctx->ext_res_off() + 2 * ctx->mh.R; p < n; ++p) otf |= fixed[p] == 0;
   if (otf != ctx->otf) {
     ctx->otf = otf;
     ctx->launch_dirty = true;
@@ -434,10 +469,14 @@ int mipwa_set_fixed(mipwa_ctx* ctx, const unsigned char* fixed, int n) {
 
 int mipwa_set_params(mipwa_ctx* ctx, const double* theta, int n) {
   if (!ctx) return MIPWA_E_INVAL;
-  if (!theta || n != ctx->mh.P) return ctx->fail(MIPWA_E_INVAL, "theta must have P entries");
-  int rc = ctx->mh.check_theta(theta, ctx->err);
+  if (!theta || n != ctx->ext_P()) return ctx->fail(MIPWA_E_INVAL, "theta must have P entries");
+  for (int p = 0; p < n; ++p)
+    if (!std::isfinite(theta[p])) return ctx->fail(MIPWA_E_INVAL, "theta has a non-finite entry");
+  std::vector<double> in(ctx->mh.P);
+  ctx->to_internal(theta, in.data());
+  int rc = ctx->mh.check_theta(in.data(), ctx->err);
   if (rc) return rc;
-  ctx->theta.assign(theta, theta + n);
+  ctx->theta.swap(in);
   ctx->have_theta = true;
   return MIPWA_OK;
 }
@@ -449,7 +488,7 @@ int mipwa_eval(mipwa_ctx* ctx, double* nll, double* grad) {
   if (rc) return rc;
   const double* o = ctx->h_out.as<double>();
   if (nll) *nll = o[0];
-  if (grad) std::memcpy(grad, o + 1, ctx->mh.P * sizeof(double));
+  if (grad) std::memcpy(grad, o + 1, ctx->ext_P() * sizeof(double));
   if (!std::isfinite(o[0])) {
     if (nll) *nll = INFINITY;
     return ctx->fail(MIPWA_E_DOMAIN, "-2 ln L is not finite (|A|^2 = 0 at an event?)");

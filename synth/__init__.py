@@ -40,6 +40,10 @@ RHO770 = Resonance("rho(770)", 1, 0.775, 0.149)
 F2_1270 = Resonance("f2(1270)", 2, 1.2755, 0.1867)
 RHO1450 = Resonance("rho(1450)", 1, 1.465, 0.4)
 PHI1020 = Resonance("phi(1020)", 1, 1.019461, 0.004249)
+# scalars of an isobar S-wave (Sec. 2 names the form, not the states): synthetic values near the
+# f0(980) and f0(1370), plain Breit-Wigners
+F0_980 = Resonance("f0(980)", 0, 0.990, 0.060)
+F0_1370 = Resonance("f0(1370)", 0, 1.350, 0.350)
 
 
 @dataclass(frozen=True)
@@ -204,7 +208,8 @@ def n_params(n_knots: int, n_res: int) -> int:
 # that, with knot magnitudes drawn from U(0.5, 2), rho(770) carries roughly half the rate of the
 # S-wave and the other waves a few to ten per cent of it.  In K-K+K+ the phi(1020) magnitude gives it
 # about 10% of the rate and the S-wave about 90%, the split Sec. 4 reports.
-TRUTH_C_MAG = {"rho(770)": 0.16, "f2(1270)": 0.32, "rho(1450)": 0.4, "phi(1020)": 0.055}
+TRUTH_C_MAG = {"rho(770)": 0.16, "f2(1270)": 0.32, "rho(1450)": 0.4, "phi(1020)": 0.055,
+               "f0(980)": 0.25, "f0(1370)": 0.6}
 
 
 def truth_theta(n_knots: int, resonances, seed: int) -> np.ndarray:
@@ -314,7 +319,39 @@ C4 = Workload("dpipipi_5M_shapes", 4, "fp64", 5_000_000, 5_000_000, 50, (RHO770,
               float_shapes=True)
 # The decay studied in the paper (Sec. 4): D+ -> K- K+ K+, 40 knots, phi(1020) P-wave, 100k toy events.
 KKK = Workload("dkkk_100k", 6, "fp64", 100_000, 1_000_000, 40, (PHI1020,), "flat", decay=D_KKK)
-WORKLOADS = {w.index: w for w in (C1, C2, C3, C4, KKK)}
+# isobar S-wave (constant non-resonant term + the two scalars) with the P and D waves of C1; the
+# two "knots" only carry the constant in the library's isobar form
+ISO = Workload("dpipipi_isobar", 7, "fp64", 10_000, 100_000, 2, (F0_980, F0_1370, RHO770, F2_1270), "flat")
+WORKLOADS = {w.index: w for w in (C1, C2, C3, C4, KKK, ISO)}
+
+
+def isobar_truth(resonances, seed: int) -> np.ndarray:
+    """Isobar-form parameters [|c_NR|, arg c_NR, (|c_r|, arg c_r)_r, (m_r, Gamma_r)_r]: c_NR = 1 at a
+    phase drawn from U(-pi, pi), the first resonance the phase reference, the other phases drawn from
+    U(-pi, pi), table masses and widths."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = len(resonances)
+    th = np.empty(2 + 4 * R)
+    th[0], th[1] = 1.0, rng.uniform(-math.pi, math.pi)
+    args = rng.uniform(-math.pi, math.pi, max(R - 1, 0))
+    for r, res in enumerate(resonances):
+        th[2 + 2 * r] = TRUTH_C_MAG[res.name]
+        th[3 + 2 * r] = 0.0 if r == 0 else args[r - 1]
+    for r, res in enumerate(resonances):
+        th[2 + 2 * R + 2 * r] = res.mass
+        th[3 + 2 * R + 2 * r] = res.width
+    return th
+
+
+def isobar_fixed(n_res: int, float_shapes: bool = False) -> np.ndarray:
+    """1 = held fixed: the first resonance coefficient (phase and scale reference) and, unless
+    float_shapes, the masses and widths."""
+    fx = np.zeros(2 + 4 * n_res, dtype=np.uint8)
+    if n_res:
+        fx[2:4] = 1
+    if not float_shapes:
+        fx[2 + 2 * n_res:] = 1
+    return fx
 
 # Serving workload: 256 toy-fit jobs, event counts log-uniform in [1e4, 5e6], knots in {20,30,40,50},
 # model as the small fit, shapes fixed, shared normalisation sample.
