@@ -104,6 +104,18 @@ int mipwa_n_params(const mipwa_ctx* ctx);
 enum { MIPWA_SWAVE_POLAR = 0, MIPWA_SWAVE_CARTESIAN = 1, MIPWA_SWAVE_ISOBAR = 2 };
 int mipwa_set_swave_form(mipwa_ctx* ctx, int form);
 
+/* How the normalisation integral I of Sec. 4 (recomputed at every evaluation) is formed:
+ *   MIPWA_NORM_POINTS (default): a sweep over the normalisation points at every evaluation;
+ *   MIPWA_NORM_QFORM: while every mass and width is fixed, A is linear in the spline polynomial
+ *     coefficients of the two intervals of a point and in the c_r, so I is a sum over the occupied
+ *     spline cells of v^T M_c conj(v) with per-cell moment matrices M_c of size (8 + R)^2, formed in
+ *     one pass over the points whenever the resonance amplitudes are rebuilt.  Each evaluation then
+ *     reads the moments instead of the points.  The same quantity up to rounding (an algebraic
+ *     rearrangement, not a method of the paper); with a mass or width floated the point sweep is used.
+ * Takes effect at the next evaluation.  Errors: E_INVAL (unknown mode). */
+enum { MIPWA_NORM_POINTS = 0, MIPWA_NORM_QFORM = 1 };
+int mipwa_set_norm_mode(mipwa_ctx* ctx, int mode);
+
 /* Data events (the sample whose likelihood is maximised, Sec. 2).  s12[i], s13[i] are host arrays of n
  * doubles, each event inside the Dalitz region to within 1e-9 (M - m3)^2.  eff (nullable) gives the
  * efficiency at each event; it enters only the constant -2 sum ln eff.  If eff is NULL and an efficiency

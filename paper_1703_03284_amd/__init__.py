@@ -17,6 +17,7 @@ __all__ = ["Context", "Server", "MipwaError", "Resonance", "FitResult", "FP64", 
 
 FP64, MIXED = L.MIPWA_FP64, L.MIPWA_MIXED
 SWAVE_POLAR, SWAVE_CARTESIAN, SWAVE_ISOBAR = 0, 1, 2
+NORM_POINTS, NORM_QFORM = 0, 1
 
 
 class MipwaError(RuntimeError):
@@ -121,6 +122,10 @@ class Context:
         nx, ny = t.shape
         self._check(self._lib.mipwa_set_eff_table(self._h, t.ctypes.data_as(C.POINTER(C.c_float)), nx, ny,
                                                   float(lo), float(hi)), "set_eff_table")
+
+    def set_norm_mode(self, mode):
+        """NORM_POINTS (default) or NORM_QFORM (per-cell moments while the shapes are fixed)."""
+        self._check(self._lib.mipwa_set_norm_mode(self._h, int(mode)), "set_norm_mode")
 
     def set_swave_form(self, form):
         """SWAVE_POLAR (default), SWAVE_CARTESIAN or SWAVE_ISOBAR (two-knot model); resets theta and

@@ -48,6 +48,7 @@ SIGNATURES = {
     "mipwa_strerror": (C.c_char_p, [C.c_int]),
     "mipwa_n_params": (C.c_int, [_P]),
     "mipwa_set_swave_form": (C.c_int, [_P, C.c_int]),
+    "mipwa_set_norm_mode": (C.c_int, [_P, C.c_int]),
     "mipwa_load_events": (C.c_int, [_P, _D, _D, _D, _I64]),
     "mipwa_load_norm": (C.c_int, [_P, _D, _D, _D, _D, _I64]),
     "mipwa_set_eff_table": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int, C.c_int, C.c_double, C.c_double]),

@@ -21,6 +21,10 @@ struct mipwa_ctx {
   bool have_theta = false;
   std::vector<unsigned char> fixed;  // external layout (ext_P entries)
   int swave = mipwa::kSwavePolar;    // parameter form seen through the C ABI
+  // normalisation as a quadratic form over per-cell moments (fixed shapes only)
+  bool qform = false;
+  bool mom_valid = false;
+  mipwa::DevBuf d_mom;
   bool otf = false;
 
   std::vector<double> cache_shape;
@@ -71,6 +75,7 @@ struct mipwa_ctx {
 
   int fail(int code, const std::string& msg);
   // external parameter count and the offset of the resonance coefficients in the external layout
+  bool use_qform() const { return qform && !otf && nm.loaded && nm.n_cells > 0; }
   int ext_P() const { return swave == mipwa::kSwaveIsobar ? 2 + 4 * mh.R : mh.P; }
   int ext_res_off() const { return swave == mipwa::kSwaveIsobar ? 2 : 2 * mh.N; }
   // external theta -> internal (polar spline) theta

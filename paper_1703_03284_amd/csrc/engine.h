@@ -61,7 +61,8 @@ struct Segment {
   double* records;    // n_blocks x rs
   long long n;        // number of points
   int n_tiles;
-  int kind;           // 0 = data, 1 = normalisation
+  int kind;           // 0 = data, 1 = normalisation points, 2 = normalisation as a quadratic form
+                      // (kind 2: tiles = the cells, n_tiles = their number, cache = their moments)
   int nint;           // N - 1 spline intervals
   int rs;             // record size in doubles
   int n_blocks;       // blocks assigned to this segment
@@ -123,6 +124,12 @@ hipError_t launch_reduce(const Segment* d_segs, const Job* d_jobs, const int2* d
 hipError_t launch_upload(void* d_dst, const void* h_src_dev, size_t bytes, hipStream_t stream);
 hipError_t launch_integrals(bool fp64, int R, const Segment* h_seg, const void* w_override,
                             double* d_records, int n_blocks, double* d_out, hipStream_t stream);
+// Moments of the normalisation points per spline cell for the quadratic form of I (fixed shapes):
+// M_c[i][j] = sum_p w_p phi_i(p) conj(phi_j(p)) over the points of cell c, with
+// phi = (t12^0..3, t13^0..3, R_1..R_R), stored as complex FP64, K = 8 + R, row-major [c][i][j].
+inline int qform_dim(int R) { return 8 + R; }
+hipError_t launch_moments(bool fp64, int R, const Segment* h_norm, const Tile* d_cells, int n_cells, double* d_mom,
+                          hipStream_t stream);
 hipError_t launch_eff_lookup(const double* d_s12, const double* d_s13, long long n, const float* d_table,
                              int nx, int ny, double lo, double hi, double* d_eps, hipStream_t stream);
 

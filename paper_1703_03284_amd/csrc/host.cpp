@@ -365,12 +365,14 @@ int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, con
     std::vector<long long> pos(start.begin(), start.end() - 1);
     for (long long i = 0; i < n; ++i) order[pos[(size_t)ja[i] * nint + jb[i]]++] = i;
   }
-  std::vector<Tile> tiles;
+  std::vector<Tile> tiles, cells;
   tiles.reserve(n / kTile + ncell);
   for (size_t c = 0; c < ncell; ++c) {
     const long long lo = start[c], hi = start[c + 1];
+    if (hi > lo) cells.push_back(Tile{(int)(c / nint), (int)(c % nint), (int)tiles.size(), 0});
     for (long long t = lo; t < hi; t += kTile)
       tiles.push_back(Tile{(int)(c / nint), (int)(c % nint), (int)t, (int)std::min<long long>(kTile, hi - t)});
+    if (hi > lo) cells.back().count = (int)tiles.size() - cells.back().start;
   }
   std::vector<double> wsorted, wplain;
   double c_eps = 0.0;
@@ -399,6 +401,12 @@ int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, con
     err = "copy of tiles failed";
     return MIPWA_E_HIP;
   }
+  if (ps.cells.alloc(std::max<size_t>(cells.size(), 1) * sizeof(Tile)) != hipSuccess ||
+      hipMemcpy(ps.cells.p, cells.data(), cells.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess) {
+    err = "upload of the cell list failed";
+    return MIPWA_E_HIP;
+  }
+  ps.n_cells = (int)cells.size();
   if (kind == 0) {
     ps.w.release();
     ps.wplain.release();

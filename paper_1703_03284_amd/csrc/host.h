@@ -111,7 +111,8 @@ struct ModelHost {
 struct PointSet {
   long long n = 0;
   int n_tiles = 0;
-  DevBuf tt, ss, w, wplain, cache, tiles;
+  int n_cells = 0;          // spline cells (j12, j13) holding points: Tile{j12, j13, first tile, tiles}
+  DevBuf tt, ss, w, wplain, cache, tiles, cells;
   double c_eps = 0.0;       // -2 sum ln eff (events)
   bool loaded = false;
 };

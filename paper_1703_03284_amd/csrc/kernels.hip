@@ -437,6 +437,132 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
 }
 
 // ---------------------------------------------------------------------------------------------
+// Normalisation as a quadratic form (fixed shapes).  In cell c the amplitude is linear in
+// v = (P_0..3 of interval j12, P_0..3 of interval j13, c_1..c_R) with the per-point functions phi of
+// the moments, so I_c = sum_p w |phi . v|^2 = sum_ij v_i M_ij conj(v_j) and the complex partials of I
+// are 2 (M^T v).  A wave takes a contiguous run of cells; lane l < K forms Y_l = (M^T v)_l, adds
+// 4 Y into the interval bins and c_r partials (the form the point sweep uses, seed 4 w A) and
+// Re(conj(v_l) Y_l) into I.
+
+template <typename Real, int R>
+__device__ void run_qform(const Segment& sg, const Real* tab, double* bins, double* scal, int wave, int lane,
+                          int waves, int local_block) {
+  constexpr int K = 8 + R;
+  const long long nw = (long long)sg.n_blocks * waves;
+  const long long gw = (long long)local_block * waves + wave;
+  const int c0 = (int)(sg.n_tiles * gw / nw);
+  const int c1 = (int)(sg.n_tiles * (gw + 1) / nw);
+  const double* __restrict__ mom = (const double*)sg.cache;
+  const Real* cv = tab + 8 * sg.nint;
+  double acc = 0.0, gre = 0.0, gim = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const Tile cell = sg.tiles[c];
+    double vr[K], vi[K];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      vr[m] = (double)tab[8 * cell.j12 + 2 * m];
+      vi[m] = (double)tab[8 * cell.j12 + 2 * m + 1];
+      vr[4 + m] = (double)tab[8 * cell.j13 + 2 * m];
+      vi[4 + m] = (double)tab[8 * cell.j13 + 2 * m + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      vr[8 + r] = (double)cv[2 * r];
+      vi[8 + r] = (double)cv[2 * r + 1];
+    }
+    double yr = 0.0, yi = 0.0, ur = 0.0, ui = 0.0;
+    if (lane < K) {
+      const double* Mc = mom + (long long)c * K * K * 2;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const double mr = Mc[2 * (i * K + lane)], mi = Mc[2 * (i * K + lane) + 1];
+        yr += mr * vr[i] - mi * vi[i];
+        yi += mr * vi[i] + mi * vr[i];
+      }
+#pragma unroll
+      for (int i = 0; i < K; ++i)
+        if (i == lane) {
+          ur = vr[i];
+          ui = vi[i];
+        }
+      acc += ur * yr + ui * yi;
+    }
+    // interval bins: the j12 lanes and the j13 lanes in two steps (the same interval when j12 == j13)
+    if (lane < 4) {
+      bins[8 * cell.j12 + 2 * lane] += 4.0 * yr;
+      bins[8 * cell.j12 + 2 * lane + 1] += 4.0 * yi;
+    }
+    if (lane >= 4 && lane < 8) {
+      bins[8 * cell.j13 + 2 * (lane - 4)] += 4.0 * yr;
+      bins[8 * cell.j13 + 2 * (lane - 4) + 1] += 4.0 * yi;
+    }
+    if (lane >= 8 && lane < K) {
+      gre += 4.0 * yr;
+      gim += 4.0 * yi;
+    }
+  }
+  const int nsc = 1 + 2 * R;
+  double* my = scal + wave * nsc;
+  {
+    const double v = wave_sum(acc);
+    if (lane == 0) my[0] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double a = wave_sum(lane == 8 + r ? gre : 0.0);
+    const double b = wave_sum(lane == 8 + r ? gim : 0.0);
+    if (lane == 0) {
+      my[1 + 2 * r] = a;
+      my[2 + 2 * r] = b;
+    }
+  }
+}
+
+// One block per cell; thread k < K*K forms M[i][j] (i = k / K, j = k % K) over the cell's points.
+template <typename Real, int R>
+__global__ __launch_bounds__(256) void k_moments(Segment sg, const Tile* __restrict__ cells, double* __restrict__ mom) {
+  constexpr int K = 8 + R;
+  using V2 = typename Ops<Real>::V2;
+  const Tile cell = cells[blockIdx.x];
+  const int k = threadIdx.x;
+  if (k >= K * K) return;
+  const int i = k / K, j = k % K;
+  const V2* __restrict__ tt = (const V2*)sg.tt;
+  const Real* __restrict__ ww = (const Real*)sg.w;
+  const V2* __restrict__ cache = (const V2*)sg.cache;
+  auto phi = [&](int q, long long p, double t12, double t13, double& re, double& im) {
+    im = 0.0;
+    if (q < 4) {
+      re = q == 0 ? 1.0 : q == 1 ? t12 : q == 2 ? t12 * t12 : t12 * t12 * t12;
+    } else if (q < 8) {
+      re = q == 4 ? 1.0 : q == 5 ? t13 : q == 6 ? t13 * t13 : t13 * t13 * t13;
+    } else {
+      const V2 c = cache[(long long)(q - 8) * sg.n + p];
+      re = (double)c.x;
+      im = (double)c.y;
+    }
+  };
+  double sr = 0.0, si = 0.0;
+  for (int t = cell.start; t < cell.start + cell.count; ++t) {
+    const Tile td = sg.tiles[t];
+    for (int q = 0; q < td.count; ++q) {
+      const long long p = (long long)td.start + q;
+      const V2 x = tt[p];
+      const double w = (double)ww[p];
+      double ar, ai, br, bi;
+      phi(i, p, (double)x.x, (double)x.y, ar, ai);
+      phi(j, p, (double)x.x, (double)x.y, br, bi);
+      // w phi_i conj(phi_j)
+      sr += w * (ar * br + ai * bi);
+      si += w * (ai * br - ar * bi);
+    }
+  }
+  double* out = mom + ((long long)blockIdx.x * K * K + k) * 2;
+  out[0] = sr;
+  out[1] = si;
+}
+
+// ---------------------------------------------------------------------------------------------
 // FP64 finish of one job, run by the job's block of k_job_finish once its records are reduced:
 //   -2 ln L = -2 S_data + C_eps + 2 n ln I,  scale = n / I,
 //   spline-polynomial partials -> knot values z and second derivatives M -> z through M = K z,
@@ -614,10 +740,14 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
   for (int i = threadIdx.x; i < waves * stride + waves * nsc; i += blockDim.x) bins[i] = 0.0;
   __syncthreads();
   const Real* tab = (const Real*)tab_lds;
-  if (sg.kind == 0)
+  if (sg.kind == 0) {
     run_segment<Real, R, OTF, 0>(sg, kin, tab, bins + wave * stride, scal, wave, lane, waves, bm.y);
-  else
+  } else if (sg.kind == 1) {
     run_segment<Real, R, OTF, 1>(sg, kin, tab, bins + wave * stride, scal, wave, lane, waves, bm.y);
+  } else {
+    // the quadratic form needs the resonance amplitudes fixed: never set up with shapes floated
+    if constexpr (!OTF) run_qform<Real, R>(sg, tab, bins + wave * stride, scal, wave, lane, waves, bm.y);
+  }
   __syncthreads();
   const int rs = sg.rs;
   double* rec = sg.records + (long long)bm.y * rs;
@@ -1071,6 +1201,26 @@ hipError_t launch_upload(void* d_dst, const void* h_src_dev, size_t bytes, hipSt
   const int blocks = (int)std::min<long long>((n + 255) / 256, 64);
   k_upload<<<blocks, 256, 0, st>>>(static_cast<const uint4*>(h_src_dev), static_cast<uint4*>(d_dst), n);
   return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t moments_impl(int R, const Segment* s, const Tile* cells, int n_cells, double* mom, hipStream_t st) {
+  switch (R) {
+    case 0: k_moments<Real, 0><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
+    case 1: k_moments<Real, 1><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
+    case 2: k_moments<Real, 2><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
+    case 3: k_moments<Real, 3><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
+    case 4: k_moments<Real, 4><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(bool fp64, int R, const Segment* s, const Tile* cells, int n_cells, double* mom,
+                          hipStream_t st) {
+  (void)hipGetLastError();
+  if (n_cells <= 0) return hipSuccess;
+  return fp64 ? moments_impl<double>(R, s, cells, n_cells, mom, st) : moments_impl<float>(R, s, cells, n_cells, mom, st);
 }
 
 hipError_t launch_integrals(bool fp64, int R, const Segment* s, const void* w, double* rec, int nb, double* out,

@@ -69,11 +69,20 @@ int mipwa_ctx::rebuild_launch() {
   HIPCHK(hipStreamSynchronize(stream), "stream sync");
   const int waves = waves_cfg ? waves_cfg : 4;
   waves_eff = waves;
-  const int total_tiles = ev.n_tiles + nm.n_tiles;
-  const int B = std::max(2, std::min(blocks_cfg, std::max(2, total_tiles / (2 * waves))));
-  nb_d = (int)std::llround((double)B * ev.n_tiles / std::max(total_tiles, 1));
-  nb_d = std::min(std::max(nb_d, 1), B - 1);
-  nb_n = B - nb_d;
+  const bool qf = use_qform();
+  int B;
+  if (qf) {
+    // the data stream gets the blocks; the cells of the quadratic form a few blocks of ~4 cells per wave
+    nb_d = std::max(1, std::min(blocks_cfg, std::max(1, ev.n_tiles / (2 * waves))));
+    nb_n = std::min(64, std::max(1, (nm.n_cells + 4 * waves - 1) / (4 * waves)));
+    B = nb_d + nb_n;
+  } else {
+    const int total_tiles = ev.n_tiles + nm.n_tiles;
+    B = std::max(2, std::min(blocks_cfg, std::max(2, total_tiles / (2 * waves))));
+    nb_d = (int)std::llround((double)B * ev.n_tiles / std::max(total_tiles, 1));
+    nb_d = std::min(std::max(nb_d, 1), B - 1);
+    nb_n = B - nb_d;
+  }
   n_blocks = B;
   const int nint = mh.N - 1;
   rs = record_size(nint, mh.R, otf);
@@ -110,7 +119,16 @@ int mipwa_ctx::rebuild_launch() {
     sg[k].job = 0;
     sg[k].g0 = k ? G_d : 0;
   }
-  std::memcpy(h_segs, sg, sizeof(sg));
+  std::memcpy(h_segs, sg, sizeof(sg));  // the point streams: cache builds and the moment pass use them
+  if (qf) {
+    const int K = qform_dim(mh.R);
+    HIPCHK(d_mom.alloc((size_t)nm.n_cells * K * K * 2 * sizeof(double)), "moment allocation");
+    sg[1].kind = 2;
+    sg[1].tiles = nm.cells.as<Tile>();
+    sg[1].n_tiles = nm.n_cells;
+    sg[1].cache = d_mom.p;
+    mom_valid = false;
+  }
   HIPCHK(d_segs.alloc(sizeof(sg)), "segment allocation");
   HIPCHK(hipMemcpy(d_segs.p, sg, sizeof(sg), hipMemcpyHostToDevice), "segment upload");
   // job 0 writes the results into mapped pinned host memory (synchronous evaluations), job 1 into
@@ -193,6 +211,7 @@ int mipwa_ctx::ensure_cache(hipStream_t st) {
   }
   cache_shape.assign(theta.begin() + 2 * mh.N + 2 * mh.R, theta.end());
   cache_valid = ev.loaded && nm.loaded;
+  mom_valid = false;  // the moments hold the normalisation points' resonance amplitudes
   return MIPWA_OK;
 }
 
@@ -235,6 +254,12 @@ int mipwa_ctx::prepare_eval(hipStream_t st) {
   if (!otf && shapes_changed()) {
     rc = ensure_cache(st);
     if (rc) return rc;
+  }
+  if (use_qform() && !mom_valid) {
+    mipwa_ctx* ctx = this;
+    HIPCHK(launch_moments(fp64, mh.R, &h_segs[1], nm.cells.as<Tile>(), nm.n_cells, d_mom.as<double>(), st),
+           "moment pass");
+    mom_valid = true;
   }
   return MIPWA_OK;
 }
@@ -390,6 +415,15 @@ void mipwa_destroy(mipwa_ctx* ctx) {
 const char* mipwa_last_error(const mipwa_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
 
 int mipwa_n_params(const mipwa_ctx* ctx) { return ctx ? ctx->ext_P() : MIPWA_E_INVAL; }
+
+int mipwa_set_norm_mode(mipwa_ctx* ctx, int mode) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (mode != MIPWA_NORM_POINTS && mode != MIPWA_NORM_QFORM) return ctx->fail(MIPWA_E_INVAL, "unknown mode");
+  ctx->qform = mode == MIPWA_NORM_QFORM;
+  ctx->launch_dirty = true;
+  ctx->mom_valid = false;
+  return MIPWA_OK;
+}
 
 int mipwa_set_swave_form(mipwa_ctx* ctx, int form) {
   if (!ctx) return MIPWA_E_INVAL;

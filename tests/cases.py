@@ -44,6 +44,35 @@ class Problem:
         n = len(self.events[0])
         return 2.0 * float(np.sum(np.abs(np.log(a.real ** 2 + a.imag ** 2)))) + 2.0 * n * abs(np.log(I))
 
+    def grad_scale(self, theta=None):
+        """Per parameter (knots and coefficients; shapes 0): the sum over points of the magnitudes of
+        the terms whose sum is the gradient, |g_p| |dA_p/dtheta| with the data seed |g| = 4/|A| and the
+        normalisation seed (n/I) 4 w |A|.  Rounding of FP32 inputs shared by all points (a coefficient,
+        cached amplitudes) is coherent across those terms, so the mixed-precision error of a component
+        whose data and normalisation sums cancel scales with this, not with the gradient."""
+        from oracle import spline as sp
+        th = self.theta if theta is None else theta
+        m = self.model
+        N, R = m.n_knots, m.n_res
+        z, c, _, _ = m.unpack(th)
+        n = len(self.events[0])
+        n12, n13, w = self.oracle_norm()
+        I = L.norm_integral(m, th, (n12, n13, w))
+        kn = m.knot_array
+        out = np.zeros(m.n_params)
+        for (s12, s13), seed in ((self.events, lambda a: 4.0 / np.abs(a)),
+                                 ((n12, n13), lambda a: (n / I) * 4.0 * w * np.abs(a))):
+            _, rs, a = L.components(m, th, s12, s13)
+            g = seed(a)
+            bz = np.abs(sp.basis_adjoint(kn, s12, g.astype(complex))) + np.abs(sp.basis_adjoint(kn, s13, g.astype(complex)))
+            out[0:2 * N:2] += bz
+            out[1:2 * N:2] += np.abs(z) * bz
+            for r in range(R):
+                t = float(np.sum(g * np.abs(rs[r])))
+                out[2 * N + 2 * r] += t
+                out[2 * N + 2 * r + 1] += abs(c[r]) * t
+        return out
+
     def context(self, precision, table_mode=False):
         from paper_1703_03284_amd import context_for
         ctx = context_for(self.workload.decay, self.knots, self.workload.resonances, precision)
