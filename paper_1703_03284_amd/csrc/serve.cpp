@@ -3,13 +3,13 @@
 // Each submitted job is a maximum-likelihood fit (the fit of Sec. 2 / Sec. 4 on a toy sample) of its
 // own events against a normalisation sample shared by the server.  Jobs wait in a queue until their
 // device footprint fits the HBM budget; an admitted job loads its events (cell sort, resonance cache)
-// and builds the resonance cache of the shared normalisation points at its own masses and widths, on
-// its own stream and thread, then runs the BFGS fit in that thread.  The normalisation points are
-// cell-sorted once per knot grid and shared.  Every evaluation a job asks for is posted to the
-// scheduler, which gathers the pending evaluations of all active jobs into one launch of the
-// streaming kernel (one data segment and one normalisation segment per job; the normalisation
-// segments of jobs sharing a knot grid read the same coordinates, weights and tiles, and their blocks
-// are interleaved so that the same tiles are read close together in time).  Jobs that become active while a step
+// and forms, at its own (fixed) masses and widths, the per-cell moments of the shared normalisation
+// points, on its own stream and thread, then runs the BFGS fit in that thread.  The normalisation
+// points are cell-sorted once per knot grid and shared; with the shapes fixed, each evaluation takes
+// the normalisation integral as a quadratic form over the job's moments instead of a sweep over the
+// points.  Every evaluation a job asks for is posted to the scheduler, which gathers the pending
+// evaluations of all active jobs into one launch of the streaming kernel (one data segment and one
+// cell segment per job).  Jobs that become active while a step
 // runs join the next step.  A job's block count depends only on its own sizes, so its reduction
 // order, and therefore its result, is bitwise the same alone or in any mix.
 #include <hip/hip_runtime.h>
@@ -75,6 +75,9 @@ struct SJob {
   int nb_d = 0, G_d = 0, G_n = 0, rs = 0;
   DevBuf d_rec, d_grec, d_consts, d_tab;
   DevBuf d_ncache;  // resonance amplitudes of the shared normalisation points at this job's shapes
+                    // (only while loading: the moments below are formed from them)
+  DevBuf d_mom;     // per-cell moments of the normalisation points: I as a quadratic form
+  int nb_q = 0;     // blocks of the job's normalisation (cell) segment
   size_t bytes = 0;
   JobState state = QUEUED;
   int status = MIPWA_OK;
@@ -252,6 +255,7 @@ void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
   J->d_grec.release();
   J->d_consts.release();
   J->d_ncache.release();
+  J->d_mom.release();
   S->used -= J->bytes;
   S->running -= 1;
   S->cv_done.notify_all();
@@ -282,8 +286,9 @@ static void serve_worker(mipwa_server* S, SJob* J) {
     const size_t real = S->fp64 ? 8 : 4;
     J->norm = ns;
     J->nb_d = seg_blocks(J->ev.n_tiles);
+    J->nb_q = std::min(64, std::max(1, (ns->ps.n_cells + 4 * kServeWaves - 1) / (4 * kServeWaves)));
     J->G_d = n_groups(J->nb_d);
-    J->G_n = n_groups(ns->nb);
+    J->G_n = n_groups(J->nb_q);
     J->rs = record_size(J->mh.N - 1, J->mh.R, false);
     const int ni = J->mh.N - 2;
     std::vector<double> cst(consts_words(J->mh.N));
@@ -293,23 +298,34 @@ static void serve_worker(mipwa_server* S, SJob* J) {
     }
     std::copy(J->mh.h.begin(), J->mh.h.end(), cst.begin() + 2 * ni);
     if (J->mh.upload_res64(J->theta0.data(), J->d_tab) != MIPWA_OK ||
-        J->d_rec.alloc((size_t)(J->nb_d + ns->nb) * J->rs * 8) ||
+        J->d_rec.alloc((size_t)(J->nb_d + J->nb_q) * J->rs * 8) ||
         J->d_grec.alloc((size_t)(J->G_d + J->G_n) * J->rs * 8) ||
         J->d_consts.alloc(cst.size() * 8) ||
-        J->d_ncache.alloc((size_t)std::max(J->mh.R, 1) * 2 * ns->ps.n * real)) {
+        J->d_ncache.alloc((size_t)std::max(J->mh.R, 1) * 2 * ns->ps.n * real) ||
+        J->d_mom.alloc((size_t)std::max(ns->ps.n_cells, 1) * qform_dim(J->mh.R) * qform_dim(J->mh.R) * 16)) {
       rc = MIPWA_E_NOMEM;
       err = "device allocation for a job failed";
     } else {
       sgn.cache = J->d_ncache.p;
+      // the full point segment of the normalisation set for the moment pass
+      Segment pts = sgn;
+      pts.tt = ns->ps.tt.p;
+      pts.w = ns->ps.w.p;
+      pts.tiles = ns->ps.tiles.as<Tile>();
+      pts.n_tiles = ns->ps.n_tiles;
+      pts.kind = 1;
       if (hipMemcpy(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
           launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
           launch_cache(S->fp64, J->mh.R, &sgn, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
+          launch_moments(S->fp64, J->mh.R, &pts, ns->ps.cells.as<Tile>(), ns->ps.n_cells, J->d_mom.as<double>(),
+                         st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) {
         rc = MIPWA_E_HIP;
         err = "loading a job failed";
       }
     }
     J->d_tab.release();
+    J->d_ncache.release();
   }
   (void)hipStreamDestroy(st);
   if (rc) {
@@ -382,7 +398,7 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
     std::map<NormSet*, std::vector<int>> by_norm;
     for (int j = 0; j < nj; ++j) by_norm[js[j]->norm].push_back(j);
     for (auto& nk : by_norm)
-      for (int b = 0; b < nk.first->nb; ++b)
+      for (int b = 0; b < js[nk.second[0]]->nb_q; ++b)
         for (int j : nk.second) map.push_back(int2{2 * j + 1, b});
     // layout of the step's upload
     size_t off = 0;
@@ -423,19 +439,26 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
       SJob* J = js[j];
       std::memcpy(hb + o_tab[j], J->staged.data(), J->staged.size());
       const PointSet* ps[2] = {&J->ev, &J->norm->ps};
-      const int nbs[2] = {J->nb_d, J->norm->nb};
+      const int nbs[2] = {J->nb_d, J->nb_q};
       for (int k = 0; k < 2; ++k) {
         Segment& s = sg[2 * j + k];
         s.tt = ps[k]->tt.p;
         s.ss = ps[k]->ss.p;
         s.w = k ? ps[k]->w.p : nullptr;
-        s.cache = k ? J->d_ncache.p : ps[k]->cache.p;
+        s.cache = ps[k]->cache.p;
         s.tiles = ps[k]->tiles.as<Tile>();
         s.table = db + o_tab[j];
         s.records = J->d_rec.as<double>() + (size_t)(k ? J->nb_d : 0) * J->rs;
         s.n = ps[k]->n;
         s.n_tiles = ps[k]->n_tiles;
         s.kind = k;
+        if (k) {
+          // the normalisation as a quadratic form over the shared set's cells and the job's moments
+          s.kind = 2;
+          s.tiles = ps[k]->cells.as<Tile>();
+          s.n_tiles = ps[k]->n_cells;
+          s.cache = J->d_mom.p;
+        }
         s.nint = J->mh.N - 1;
         s.rs = J->rs;
         s.n_blocks = nbs[k];
