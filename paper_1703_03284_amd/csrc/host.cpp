@@ -249,173 +249,4 @@ int ModelHost::check_theta(const double* theta, std::string& err) const {
   return MIPWA_OK;
 }
 
-namespace {
-
-template <typename Real>
-int upload_sorted(const ModelHost& mh, const std::vector<double>& a, const std::vector<double>& b,
-                  const std::vector<int>& ja, const std::vector<int>& jb, const std::vector<long long>& order,
-                  const std::vector<double>* wsorted, const std::vector<double>* wplain, PointSet& ps,
-                  std::string& err) {
-  const long long n = (long long)order.size();
-  std::vector<Real> tt(2 * n);
-  std::vector<double> ss(2 * n);
-  for (long long i = 0; i < n; ++i) {
-    const long long o = order[i];
-    tt[2 * i] = Real((a[o] - mh.knots[ja[o]]) / mh.h[ja[o]]);
-    tt[2 * i + 1] = Real((b[o] - mh.knots[jb[o]]) / mh.h[jb[o]]);
-    ss[2 * i] = a[o];
-    ss[2 * i + 1] = b[o];
-  }
-  if (ps.tt.alloc(tt.size() * sizeof(Real)) != hipSuccess || ps.ss.alloc(ss.size() * sizeof(double)) != hipSuccess ||
-      ps.cache.alloc((size_t)std::max(mh.R, 1) * 2 * n * sizeof(Real)) != hipSuccess) {
-    err = "device allocation failed for points";
-    return MIPWA_E_NOMEM;
-  }
-  if (hipMemcpy(ps.tt.p, tt.data(), tt.size() * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(ps.ss.p, ss.data(), ss.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-    err = "copy of points to the device failed";
-    return MIPWA_E_HIP;
-  }
-  if (wsorted) {
-    std::vector<Real> w(n), wp(n);
-    for (long long i = 0; i < n; ++i) {
-      w[i] = Real((*wsorted)[i]);
-      wp[i] = Real((*wplain)[i]);
-    }
-    if (ps.w.alloc(n * sizeof(Real)) != hipSuccess || ps.wplain.alloc(n * sizeof(Real)) != hipSuccess) {
-      err = "device allocation failed for weights";
-      return MIPWA_E_NOMEM;
-    }
-    if (hipMemcpy(ps.w.p, w.data(), n * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(ps.wplain.p, wp.data(), n * sizeof(Real), hipMemcpyHostToDevice) != hipSuccess) {
-      err = "copy of weights to the device failed";
-      return MIPWA_E_HIP;
-    }
-  }
-  return MIPWA_OK;
-}
-
-}  // namespace
-
-int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, const double* s13, const double* w,
-                const double* eff, long long n, const EffTable& et, hipStream_t st, PointSet& ps,
-                std::string& err) {
-  ps.loaded = false;
-  if (n < 1 || !s12 || !s13 || (kind == 1 && !w)) {
-    err = kind == 1 ? "need n >= 1 points with s12, s13 and w" : "need n >= 1 events with s12 and s13";
-    return MIPWA_E_INVAL;
-  }
-  if (n > (1LL << 31) - kTile) {
-    err = "at most 2^31 points per set";
-    return MIPWA_E_INVAL;
-  }
-  const double tol = 1e-9 * mh.smax();
-  std::vector<double> a(n), b(n);
-  std::vector<int> ja(n), jb(n);
-  for (long long i = 0; i < n; ++i) {
-    const double x = s12[i], y = s13[i];
-    if (!std::isfinite(x) || !std::isfinite(y) || !mh.inside(x, y, tol)) {
-      err = "point " + std::to_string(i) + " (" + std::to_string(x) + ", " + std::to_string(y) +
-            ") is outside the Dalitz region";
-      return MIPWA_E_INVAL;
-    }
-    if (kind == 1 && !(w[i] > 0 && std::isfinite(w[i]))) {
-      err = "weight " + std::to_string(i) + " must be positive and finite";
-      return MIPWA_E_INVAL;
-    }
-    a[i] = std::min(x, y);
-    b[i] = std::max(x, y);
-    ja[i] = mh.interval(a[i]);
-    jb[i] = mh.interval(b[i]);
-  }
-  // efficiency at the points as given (not at the swapped coordinates)
-  std::vector<double> eps;
-  if (eff) {
-    eps.assign(eff, eff + n);
-    for (long long i = 0; i < n; ++i)
-      if (!(eps[i] > 0) || !std::isfinite(eps[i])) {
-        err = "efficiency " + std::to_string(i) + " must be positive and finite";
-        return MIPWA_E_INVAL;
-      }
-  } else if (et.set()) {
-    DevBuf d12, d13, de;
-    if (d12.alloc(n * 8) != hipSuccess || d13.alloc(n * 8) != hipSuccess || de.alloc(n * 8) != hipSuccess) {
-      err = "device allocation failed for the efficiency lookup";
-      return MIPWA_E_NOMEM;
-    }
-    eps.resize(n);
-    if (hipMemcpy(d12.p, s12, n * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d13.p, s13, n * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        launch_eff_lookup(d12.as<double>(), d13.as<double>(), n, et.d.as<float>(), et.nx, et.ny, et.lo, et.hi,
-                          de.as<double>(), st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess ||
-        hipMemcpy(eps.data(), de.p, n * 8, hipMemcpyDeviceToHost) != hipSuccess) {
-      err = "efficiency lookup on the device failed";
-      return MIPWA_E_HIP;
-    }
-  }
-  // stable counting sort by cell (j12, j13)
-  const int nint = mh.N - 1;
-  const size_t ncell = (size_t)nint * nint;
-  std::vector<long long> start(ncell + 1, 0);
-  for (long long i = 0; i < n; ++i) start[(size_t)ja[i] * nint + jb[i] + 1]++;
-  for (size_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
-  std::vector<long long> order(n);
-  {
-    std::vector<long long> pos(start.begin(), start.end() - 1);
-    for (long long i = 0; i < n; ++i) order[pos[(size_t)ja[i] * nint + jb[i]]++] = i;
-  }
-  std::vector<Tile> tiles, cells;
-  tiles.reserve(n / kTile + ncell);
-  for (size_t c = 0; c < ncell; ++c) {
-    const long long lo = start[c], hi = start[c + 1];
-    if (hi > lo) cells.push_back(Tile{(int)(c / nint), (int)(c % nint), (int)tiles.size(), 0});
-    for (long long t = lo; t < hi; t += kTile)
-      tiles.push_back(Tile{(int)(c / nint), (int)(c % nint), (int)t, (int)std::min<long long>(kTile, hi - t)});
-    if (hi > lo) cells.back().count = (int)tiles.size() - cells.back().start;
-  }
-  std::vector<double> wsorted, wplain;
-  double c_eps = 0.0;
-  if (kind == 0) {
-    if (!eps.empty())
-      for (long long i = 0; i < n; ++i) c_eps += -2.0 * std::log(eps[i]);
-  } else {
-    wsorted.resize(n);
-    wplain.resize(n);
-    for (long long i = 0; i < n; ++i) {
-      const long long o = order[i];
-      wplain[i] = w[o];
-      wsorted[i] = w[o] * (eps.empty() ? 1.0 : eps[o]);
-    }
-  }
-  int rc = fp64 ? upload_sorted<double>(mh, a, b, ja, jb, order, kind ? &wsorted : nullptr,
-                                        kind ? &wplain : nullptr, ps, err)
-                : upload_sorted<float>(mh, a, b, ja, jb, order, kind ? &wsorted : nullptr,
-                                       kind ? &wplain : nullptr, ps, err);
-  if (rc != MIPWA_OK) return rc;
-  if (ps.tiles.alloc(tiles.size() * sizeof(Tile)) != hipSuccess) {
-    err = "device allocation failed for tiles";
-    return MIPWA_E_NOMEM;
-  }
-  if (hipMemcpy(ps.tiles.p, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess) {
-    err = "copy of tiles failed";
-    return MIPWA_E_HIP;
-  }
-  if (ps.cells.alloc(std::max<size_t>(cells.size(), 1) * sizeof(Tile)) != hipSuccess ||
-      hipMemcpy(ps.cells.p, cells.data(), cells.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess) {
-    err = "upload of the cell list failed";
-    return MIPWA_E_HIP;
-  }
-  ps.n_cells = (int)cells.size();
-  if (kind == 0) {
-    ps.w.release();
-    ps.wplain.release();
-  }
-  ps.n = n;
-  ps.n_tiles = (int)tiles.size();
-  ps.c_eps = c_eps;
-  ps.loaded = true;
-  return MIPWA_OK;
-}
-
 }  // namespace mipwa

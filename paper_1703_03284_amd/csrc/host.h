@@ -117,9 +117,9 @@ struct PointSet {
   bool loaded = false;
 };
 
-// Load host points into a point set: validate, swap each pair to s12 <= s13, locate the spline
-// cells, stable counting sort by cell, cut tiles, compute local coordinates in FP64, upload.
-// eps_dev_fn: when no eff array is given and a table is set, eff is looked up on the device.
+// Load host points into a point set, on the device: validate, swap each pair to s12 <= s13, locate
+// the spline cells, stable sort by cell, compute local coordinates in FP64; the host cuts the tiles.
+// When no eff array is given and a table is set, eff is looked up on the device.
 struct EffTable {
   std::vector<float> tab;
   int nx = 0, ny = 0;
