@@ -61,11 +61,13 @@ def build_inputs(wl, n_events, n_norm):
     import synth
     from paper_1703_03284_amd import FP64, context_for
     d = wl.decay
-    table = synth.efficiency_histogram(synth.PolyEfficiency.seeded(d, wl.seed("eff")))
+    table = synth.efficiency_histogram(synth.PolyEfficiency.seeded(d, wl.seed("eff"))) \
+        if wl.efficiency == "hist" else None
     truth = wl.truth()
     t0 = time.time()
     gen = context_for(d, wl.knots(), wl.resonances, FP64)
-    gen.set_eff_table(table, d.smin, d.smax)
+    if table is not None:
+        gen.set_eff_table(table, d.smin, d.smax)
     ev12, ev13, fmax = gen.toy(truth, n_events, wl.seed("events"))
     gen.close()
     log(f"[bench] generated {n_events} toy events on the device in {time.time() - t0:.1f}s (fmax={fmax:.4g})")
@@ -85,20 +87,23 @@ def time_gpu(wl, precision, table, events, norm, steps, warmup, blocks=0, waves=
         ctx.set_launch(blocks, waves)
     if qform:
         ctx.set_norm_mode(NORM_QFORM)
-    ctx.set_eff_table(table, d.smin, d.smax)
+    if wl.float_shapes:
+        ctx.set_fixed(wl.fixed())   # masses and widths floated: resonances on the fly every evaluation
+    if table is not None:
+        ctx.set_eff_table(table, d.smin, d.smax)
     t0 = time.time()
     ctx.load_events(*events)
     ctx.load_norm(*norm)
     log(f"[bench] loaded {len(events[0])} + {len(norm[0])} points in {time.time() - t0:.1f}s")
     th0 = wl.start()
     rng = np.random.Generator(np.random.PCG64(12345))
-    n_shape = 4 * wl.n_res
+    n_shape = 0 if wl.float_shapes else 4 * wl.n_res
     for _ in range(warmup):
         ctx.eval(th0)
     thetas = []
     for _ in range(steps):
         th = th0.copy()
-        th[:-n_shape] += 1e-9 * rng.standard_normal(len(th) - n_shape)  # no result can be reused
+        th[:len(th) - n_shape] += 1e-9 * rng.standard_normal(len(th) - n_shape)  # no result can be reused
         thetas.append(th)
     ctx.set_timing(True)   # HIP events on the evaluation stream, accumulated by the library
     t0 = time.perf_counter()
@@ -277,12 +282,49 @@ def paper_fit(precision_name="fp64"):
             "precision": precision_name, "fits": out}
 
 
-def profile_pass(steps):
-    """A few headline evaluations plus a 1 GiB device copy of known size (counter calibration)."""
+# Arithmetic of one point with masses and widths floated, counted from the formulas as FP32 vector
+# operations (add, multiply, FMA and compare-select count one each) plus transcendentals (reciprocal,
+# square root, reciprocal square root, log).  Per pairing of the Breit-Wigner (x, y): the shared
+# kinematics (q^2, p^2, sqrt x, q, T_1, T_2) take 23 operations and 3 transcendentals; each resonance
+# takes 19 (L = 1) or 22 (L = 2) operations and 3 transcendentals for its value and 19 more for its
+# mass and width partials.  Per point: the two spline axes, |A|^2 and the spline adjoint take 36, the
+# data seed (log, reciprocal) 5 and 2 transcendentals, the normalisation seed 4; each resonance adds
+# 16 for its combination into A and its coefficient, mass and width adjoints.
+def otf_ops_per_point(spins, kind):
+    pairing = 23 + sum((19 if L == 1 else 22) + 19 for L in spins)
+    ops = 2 * pairing + 36 + (5 if kind == "data" else 4) + 16 * len(spins)
+    trans = 2 * (3 + 3 * len(spins)) + (2 if kind == "data" else 0)
+    return ops, trans
+
+
+# The vector ALU ceiling without packed FP32 math (which this build leaves off): 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz lane-operations per second; a transcendental takes four operation slots.
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+TRANS_SLOTS = 4
+
+
+def shapes_floated(steps, warmup, precision_name):
+    """The 5M + 5M workload with every mass and width floated: no resonance cache, the resonances
+    and their mass/width partials are evaluated on the fly at every point of every evaluation."""
+    import synth
+    from paper_1703_03284_amd import FP64, MIXED
+    wl = synth.C4
+    table, events, norm = build_inputs(wl, wl.n_events, wl.n_norm)
+    prec = {"mixed": MIXED, "fp64": FP64}[precision_name]
+    r = time_gpu(wl, prec, table, events, norm, steps, warmup)
+    log(f"[bench] shapes floated, {precision_name}: {r}")
+    return {"workload": f"D+->pi-pi+pi+ {wl.n_events} toy events + {wl.n_norm} uniform normalisation points, "
+                        f"{wl.n_knots} knots, rho(770)+f2(1270)+rho(1450) with masses and widths floated",
+            "precision": precision_name, "value": r["value"], "unit": "evals/s", "ms_per_step": r["ms_per_step"],
+            "device_ms_per_step": r["dev_ms"], "stream_kernel_ms": r["stream_kernel_ms"]}
+
+
+def profile_pass(steps, which="headline"):
+    """A few evaluations of one workload plus a 1 GiB device copy of known size (counter calibration)."""
     import torch
     import synth
     from paper_1703_03284_amd import MIXED
-    wl = synth.C3
+    wl = synth.C4 if which == "shapes" else synth.C3
     table, events, norm = build_inputs(wl, wl.n_events, wl.n_norm)
     r = time_gpu(wl, MIXED, table, events, norm, steps, 2)
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -307,14 +349,15 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=256)
-    ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--profile-pass", nargs="?", const="headline", choices=["headline", "shapes"])
+    ap.add_argument("--no-shapes", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the likelihood would shard "
-              "by points with one small all-reduce per evaluation; see DESIGN.md).", file=sys.stderr)
+              "by points with one small all-reduce per evaluation).", file=sys.stderr)
         sys.exit(2)
     if args.profile_pass:
-        profile_pass(args.steps)
+        profile_pass(args.steps, args.profile_pass)
         return
     n_ev_cpu = args.events or 10_000_000
     n_nm_cpu = args.norm or 10_000_000
@@ -371,6 +414,20 @@ def main():
     out["quadratic_form_norm"] = {"value": qf["value"], "ms_per_step": qf["ms_per_step"],
                                   "device_ms_per_step": qf["dev_ms"], "stream_kernel_ms": qf["stream_kernel_ms"],
                                   "nll_minus_point_sweep": qf["nll"] - mixed["nll"]}
+    if not args.no_shapes:
+        sh = {p: shapes_floated(max(10, args.steps // 4), 3, p) for p in ("mixed", "fp64")}
+        spins = [r.spin for r in synth.C4.resonances]
+        slots = 0
+        for kind, n in (("data", synth.C4.n_events), ("norm", synth.C4.n_norm)):
+            ops, trans = otf_ops_per_point(spins, kind)
+            slots += n * (ops + TRANS_SLOTS * trans)
+        sec = sh["mixed"]["stream_kernel_ms"] * 1e-3
+        sh["roofline_mixed"] = {"bound": "alu", "achieved": slots / sec / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                                "unit": "T lane-op slots/s", "frac": slots / sec / VALU_LANE_OPS_PEAK,
+                                "slots_per_launch": slots, "kernel": f"k_eval<float,{synth.C4.n_res},true>",
+                                "kernel_ms": sh["mixed"]["stream_kernel_ms"]}
+        sh["fp64"]["mixed_speedup"] = sh["mixed"]["value"] / sh["fp64"]["value"]
+        out["shapes_floated"] = sh
     if not args.no_serve:
         out["serving"] = serving(args.serve_jobs, MIXED)
     if not args.no_paper_fit:
