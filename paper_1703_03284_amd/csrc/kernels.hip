@@ -67,11 +67,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 // kappa = sqrt(N_L(z_qr) N_L(z_pr)) and delta = Gamma_r m_r^2 N_L(z_qr) / q_r^(2L+1):
 //   BW = kappa f(x) T_L(x,y) / (m_r^2 - x - i delta u(x)),
 //   f = 1/sqrt(N_L(rho^2 q^2) N_L(rD^2 p^2)),  u = q^(2L+1) / (sqrt(x) N_L(rho^2 q^2)),
-// which is B_L(q) B_L(p) T_L / (m_r^2 - x - i m_r Gamma(x)).  With DER it also adds
-//   dBW/dm = BW (dln kappa/dm - (2 m_r - i ddelta/dm u) / D),   dBW/dGamma = BW i (ddelta/dGamma) u / D.
+// which is B_L(q) B_L(p) T_L / (m_r^2 - x - i m_r Gamma(x)).  The mass and width partials are
+//   dBW/dm = dln kappa/dm BW - 2 m_r E + i (ddelta/dm) F,   dBW/dGamma = i (ddelta/dGamma) F,
+// with E = BW / D and F = u BW / D.  The constants are per resonance, so with DER the pairing adds
+// E and F to (er, ei) and (fr, fi) and the constants are applied once to the reduced sums.
 template <typename Real, int R, bool DER>
 __device__ __forceinline__ void bw_pairing(const Kin<Real>& k, const Real* __restrict__ res, Real x, Real y,
-                                           Real* br, Real* bi, Real* mr, Real* mi, Real* gr, Real* gi) {
+                                           Real* br, Real* bi, Real* er, Real* ei, Real* fr, Real* fi) {
   using O = Ops<Real>;
   const Real ix = O::rcp(x);
   Real q2 = (x - k.thr_hi) * (x - k.thr_lo) * (Real(0.25) * ix);
@@ -115,15 +117,11 @@ __device__ __forceinline__ void bw_pairing(const Kin<Real>& k, const Real* __res
     bi[r] += vi;
     if constexpr (DER) {
       const Real ire = dre * idd, iim = -dim * idd;  // 1/D
-      const Real mass = c[5], dlk = c[6], ddm = c[7], ddg = c[8];
-      const Real zr = Real(2) * mass * ire + ddm * u * iim;
-      const Real zi = Real(2) * mass * iim - ddm * u * ire;
-      const Real fr = dlk - zr, fi = -zi;
-      mr[r] += vr * fr - vi * fi;
-      mi[r] += vr * fi + vi * fr;
-      const Real hr = -ddg * u * iim, hi = ddg * u * ire;
-      gr[r] += vr * hr - vi * hi;
-      gi[r] += vr * hi + vi * hr;
+      const Real wr = vr * ire - vi * iim, wi = vr * iim + vi * ire;  // E = BW / D
+      er[r] += wr;
+      ei[r] += wi;
+      fr[r] += u * wr;
+      fi[r] += u * wi;
     }
   }
 }
@@ -225,10 +223,10 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   };
 
   // One point: both spline axes, the resonance terms, |A|^2, the seed g of the adjoint, and its
-  // products with the spline powers and the resonance amplitudes (and, on the fly, their mass and
-  // width derivatives).  Invalid lanes contribute zero.
-  auto accumulate = [&](Real x12, Real x13, const Real* rr, const Real* ri, const Real* dmr, const Real* dmi,
-                        const Real* dgr, const Real* dgi, Real wv, bool valid) {
+  // products with the spline powers and the resonance amplitudes (and, on the fly, with the sums E
+  // and F of the mass and width partials).  Invalid lanes contribute zero.
+  auto accumulate = [&](Real x12, Real x13, const Real* rr, const Real* ri, const Real* er, const Real* ei,
+                        const Real* fr, const Real* fi, Real wv, bool valid) {
     Real ar = p12[0] + x12 * (p12[2] + x12 * (p12[4] + x12 * p12[6]));
     Real ai = p12[1] + x12 * (p12[3] + x12 * (p12[5] + x12 * p12[7]));
     ar += p13[0] + x13 * (p13[2] + x13 * (p13[4] + x13 * p13[6]));
@@ -279,10 +277,10 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
       tgc[2 * r] += gr * rr[r] + gi * ri[r];
       tgc[2 * r + 1] += gi * rr[r] - gr * ri[r];
       if constexpr (OTF) {
-        thm[2 * r] += gr * dmr[r] + gi * dmi[r];
-        thm[2 * r + 1] += gi * dmr[r] - gr * dmi[r];
-        thg[2 * r] += gr * dgr[r] + gi * dgi[r];
-        thg[2 * r + 1] += gi * dgr[r] - gr * dgi[r];
+        thm[2 * r] += gr * er[r] + gi * ei[r];
+        thm[2 * r + 1] += gi * er[r] - gr * ei[r];
+        thg[2 * r] += gr * fr[r] + gi * fi[r];
+        thg[2 * r + 1] += gi * fr[r] - gr * fi[r];
       }
     }
   };
@@ -378,28 +376,50 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     }
   } else {
     // Shapes floated: amplitudes and their derivatives on the fly.  ALU-bound; one point per lane
-    // at a time keeps the register file within one wave's share.
+    // at a time keeps the register file within one wave's share, and the loads of the next point
+    // (the next in this tile, else the first of the next tile, whose descriptor is requested a
+    // tile ahead) are issued before the current point is computed.  Lanes past a tile's end
+    // re-read its last point and contribute zero.
+    if (t0 < t1) {
+      auto issue = [&](const Tile& t, int b, V2& tv, double2& sv, Real& wv) {
+        const int i = b * 64 + lane;
+        const long long p = (long long)t.start + (i < t.count ? i : t.count - 1);
+        tv = tt[p];
+        sv = ss[p];
+        if constexpr (KIND == 1) wv = ww[p];
+      };
+      Tile td = sg.tiles[t0];
+      Tile tn = sg.tiles[min(t0 + 1, t1 - 1)];
+      V2 tv;
+      double2 sv;
+      Real wv = Real(0);
+      issue(td, 0, tv, sv, wv);
 #pragma unroll 1
-    for (int ti = t0; ti < t1; ++ti) {
-      const Tile td = sg.tiles[ti];
-      enter_cell(td.j12, td.j13);
+      for (int ti = t0; ti < t1; ++ti) {
+        enter_cell(td.j12, td.j13);
 #pragma unroll 1
-      for (int ib = 0; ib < IT; ++ib) {
-        const int i = ib * 64 + lane;
-        const bool valid = i < td.count;
-        const long long p = (long long)td.start + (valid ? i : td.count - 1);
-        const V2 tv = tt[p];
-        const double2 sv = ss[p];
-        const Real wv = KIND == 1 ? ww[p] : Real(0);
-        Real rr[R1], ri[R1], dmr[R1], dmi[R1], dgr[R1], dgi[R1];
+        for (int ib = 0; ib < IT; ++ib) {
+          const bool valid = ib * 64 + lane < td.count;
+          V2 tv2;
+          double2 sv2;
+          Real wv2 = Real(0);
+          if (ib + 1 < IT) issue(td, ib + 1, tv2, sv2, wv2);
+          else issue(tn, 0, tv2, sv2, wv2);  // the last tile's own first point when none follows
+          Real rr[R1], ri[R1], er[R1], ei[R1], fr[R1], fi[R1];
 #pragma unroll
-        for (int r = 0; r < R1; ++r) rr[r] = ri[r] = dmr[r] = dmi[r] = dgr[r] = dgi[r] = Real(0);
-        const Real x12s = (Real)sv.x, x13s = (Real)sv.y;
-        bw_pairing<Real, R, true>(kin, res, x12s, x13s, rr, ri, dmr, dmi, dgr, dgi);
-        bw_pairing<Real, R, true>(kin, res, x13s, x12s, rr, ri, dmr, dmi, dgr, dgi);
-        accumulate(tv.x, tv.y, rr, ri, dmr, dmi, dgr, dgi, wv, valid);
+          for (int r = 0; r < R1; ++r) rr[r] = ri[r] = er[r] = ei[r] = fr[r] = fi[r] = Real(0);
+          const Real x12s = (Real)sv.x, x13s = (Real)sv.y;
+          bw_pairing<Real, R, true>(kin, res, x12s, x13s, rr, ri, er, ei, fr, fi);
+          bw_pairing<Real, R, true>(kin, res, x13s, x12s, rr, ri, er, ei, fr, fi);
+          accumulate(tv.x, tv.y, rr, ri, er, ei, fr, fi, wv, valid);
+          tv = tv2;
+          sv = sv2;
+          wv = wv2;
+        }
+        fold_tile();
+        td = tn;
+        tn = sg.tiles[min(ti + 2, t1 - 1)];
       }
-      fold_tile();
     }
   }
   if constexpr (!kTilePartial) {
@@ -414,6 +434,19 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     }
   }
   if (cj12 >= 0) flush();
+  if constexpr (OTF) {
+    // g conj(dR/dm) = dlk g conj(R) - 2 m g conj(E) - i ddm g conj(F),  g conj(dR/dGamma) = -i ddg g conj(F)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const Real* c = res + r * kResWords;
+      const double m2 = 2.0 * (double)c[5], dlk = (double)c[6], ddm = (double)c[7], ddg = (double)c[8];
+      const double er = ahm[2 * r], ei = ahm[2 * r + 1], fr = ahg[2 * r], fi = ahg[2 * r + 1];
+      ahm[2 * r] = dlk * agc[2 * r] - m2 * er + ddm * fi;
+      ahm[2 * r + 1] = dlk * agc[2 * r + 1] - m2 * ei - ddm * fr;
+      ahg[2 * r] = ddg * fi;
+      ahg[2 * r + 1] = -ddg * fr;
+    }
+  }
 
   const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
   double* my = scal + wave * nsc;
