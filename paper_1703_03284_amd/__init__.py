@@ -81,6 +81,16 @@ class Context:
         self.n_res = len(resonances)
         self.n_params = self._lib.mipwa_n_params(h)
         self.precision = precision
+        self._eval_buffers()
+
+    def _eval_buffers(self):
+        # theta and gradient buffers with their ctypes pointers made once: building a pointer from an
+        # array costs several microseconds, a noticeable share of one evaluation
+        n = self.n_params
+        self._th_buf, self._g_buf = np.empty(n), np.empty(n)
+        self._th_ptr, self._g_ptr = L.dptr(self._th_buf), L.dptr(self._g_buf)
+        self._nll = C.c_double()
+        self._nll_ref = C.byref(self._nll)
 
     # -- plumbing
     def _check(self, rc, what):
@@ -132,6 +142,7 @@ class Context:
         the fixed mask, and changes n_params."""
         self._check(self._lib.mipwa_set_swave_form(self._h, int(form)), "set_swave_form")
         self.n_params = self._lib.mipwa_n_params(self._h)
+        self._eval_buffers()
 
     def set_fixed(self, fixed):
         f = np.ascontiguousarray(fixed, dtype=np.uint8)
@@ -148,14 +159,16 @@ class Context:
     def eval(self, theta=None, raise_domain=True):
         """(-2 ln L, gradient) at theta (or the current parameters)."""
         if theta is not None:
-            self.set_params(theta)
-        v = C.c_double()
-        g = np.empty(self.n_params)
-        rc = self._lib.mipwa_eval(self._h, C.byref(v), L.dptr(g))
+            if np.shape(theta) != self._th_buf.shape:
+                self.set_params(theta)  # reports the length mismatch
+            self._th_buf[:] = theta
+            self._check(self._lib.mipwa_set_params(self._h, self._th_ptr, self.n_params), "set_params")
+        rc = self._lib.mipwa_eval(self._h, self._nll_ref, self._g_ptr)
+        g = self._g_buf.copy()
         if rc == -5 and not raise_domain:
             return float("inf"), g
         self._check(rc, "eval")
-        return v.value, g
+        return self._nll.value, g
 
     def eval_async(self, stream_handle: int, d_out_ptr: int):
         """Enqueue an evaluation on a HIP stream; [nll, grad...] lands at the device pointer d_out_ptr."""
