@@ -657,15 +657,24 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
   const int n = N - 2;
   for (int comp = (threadIdx.x >> 6); comp < 2 && (threadIdx.x & 63) == 0;
        comp += (blockDim.x >= 128 ? 2 : 1)) {
+    // both sweeps carry their chain in a register and have no branch in the body, so the loads of
+    // the independent operands (LDS) are issued ahead of the dependent arithmetic
     double prev = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < n; ++i) {
-      const double a = i > 0 ? h[i] : 0.0;
-      prev = (gm[2 * (i + 1) + comp] - a * prev) * thinv[i];
-      u[2 * (i + 1) + comp] = prev;
+    if (n > 0) {
+      prev = gm[2 + comp] * thinv[0];
+      u[2 + comp] = prev;
     }
 #pragma unroll 8
-    for (int i = n - 2; i >= 0; --i) u[2 * (i + 1) + comp] -= thc[i] * u[2 * (i + 2) + comp];
+    for (int i = 1; i < n; ++i) {
+      prev = (gm[2 * (i + 1) + comp] - h[i] * prev) * thinv[i];
+      u[2 * (i + 1) + comp] = prev;
+    }
+    double next = prev;
+#pragma unroll 8
+    for (int i = n - 2; i >= 0; --i) {
+      next = u[2 * (i + 1) + comp] - thc[i] * next;
+      u[2 * (i + 1) + comp] = next;
+    }
     u[comp] = 0.0;
     u[2 * (N - 1) + comp] = 0.0;
   }
@@ -813,12 +822,14 @@ __global__ __launch_bounds__(512) void k_group_sum(const Segment* __restrict__ s
   const double* rb = sg.records + (long long)g * kGroup * rs;
   double* go = jb.grec + (long long)(sg.g0 + g) * rs;
   for (int f = threadIdx.x; f < rs; f += blockDim.x) {
+    // every load reads a valid record (the index is clamped into the group) and is issued without a
+    // branch; records past the group's end are then dropped from the sum
     double v[kGroup];
 #pragma unroll
-    for (int b = 0; b < kGroup; ++b) v[b] = b < gsz ? rb[(long long)b * rs + f] : 0.0;
+    for (int b = 0; b < kGroup; ++b) v[b] = rb[(long long)min(b, gsz - 1) * rs + f];
     double s = 0.0;
 #pragma unroll
-    for (int b = 0; b < kGroup; ++b) s += v[b];
+    for (int b = 0; b < kGroup; ++b) s += b < gsz ? v[b] : 0.0;
     go[f] = s;
   }
 }
@@ -851,15 +862,19 @@ __global__ __launch_bounds__(kFinishThreads) void k_job_finish(const Job* __rest
   constexpr int FPT = 4;
   const int gmax = max(jb.G_d, jb.G_n);
   for (int f0 = threadIdx.x; f0 < nf; f0 += FPT * blockDim.x) {
+    // Loads are issued without branches: the field and the group index are clamped to valid records
+    // (every job has at least one group of each kind), and what lies past the end is dropped.
     const double* p[FPT];
-    int G[FPT];
+    int G[FPT], Gl[FPT];
     double sum[FPT];
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
       const int f = f0 + j * blockDim.x;
-      const bool nrm = f >= rs;
+      const int fc = min(f, nf - 1);
+      const bool nrm = fc >= rs;
       G[j] = f < nf ? (nrm ? jb.G_n : jb.G_d) : 0;
-      p[j] = jb.grec + (long long)(nrm ? jb.G_d : 0) * rs + (nrm ? f - rs : f);
+      Gl[j] = (nrm ? jb.G_n : jb.G_d) - 1;
+      p[j] = jb.grec + (long long)(nrm ? jb.G_d : 0) * rs + (nrm ? fc - rs : fc);
       sum[j] = 0.0;
     }
     for (int k0 = 0; k0 < gmax; k0 += 8) {
@@ -867,11 +882,11 @@ __global__ __launch_bounds__(kFinishThreads) void k_job_finish(const Job* __rest
 #pragma unroll
       for (int j = 0; j < FPT; ++j)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[j][k] = k0 + k < G[j] ? p[j][(long long)(k0 + k) * rs] : 0.0;
+        for (int k = 0; k < 8; ++k) v[j][k] = p[j][(long long)min(k0 + k, Gl[j]) * rs];
 #pragma unroll
       for (int j = 0; j < FPT; ++j)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) sum[j] += v[j][k];
+        for (int k = 0; k < 8; ++k) sum[j] += k0 + k < G[j] ? v[j][k] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < FPT; ++j)
