@@ -55,6 +55,21 @@ struct Ops<double> {
   }
 };
 
+// Streaming load that marks its lines as not worth keeping in the caches (each point is read once per
+// evaluation, and a point set is larger than the caches).
+template <typename T>
+__device__ __forceinline__ T nt_load(const T* p) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "4-, 8- or 16-byte element");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_nontemporal_load((const unsigned*)p));
+  } else if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_nontemporal_load((const unsigned long long*)p));
+  } else {
+    using U4v = unsigned __attribute__((ext_vector_type(4)));
+    return __builtin_bit_cast(T, __builtin_nontemporal_load((const U4v*)p));
+  }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -320,11 +335,11 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   };
 
   if constexpr (!OTF) {
-    // Cached amplitudes: the sweep is bound by HBM reads, so every step keeps loads in flight.  A
-    // tile is taken in two halves of HB points per lane; the loads of the next half (the second half
-    // of this tile, then the first half of the next tile) are issued before the current half is
-    // used, and the next tile's descriptor is requested a tile ahead.  Lanes past the tile end
-    // re-read its last point and contribute zero.
+    // Cached amplitudes: the sweep is bound by HBM reads (non-temporal loads), so every step keeps
+    // loads in flight.  A tile is taken in two halves of HB points per lane; the loads of the next
+    // half (the second half of this tile, then the first half of the next tile) are issued before
+    // the current half is used, and the next tile's descriptor is requested a tile ahead.  Lanes past
+    // the tile end re-read its last point and contribute zero.
     constexpr int HB = IT / 2;
     static_assert(IT % 2 == 0, "a tile holds an even number of wave-widths");
     struct Half {
@@ -337,10 +352,10 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
       for (int k = 0; k < HB; ++k) {
         const int i = (part * HB + k) * 64 + lane;
         const long long p = (long long)td.start + (i < td.count ? i : td.count - 1);
-        h.t[k] = tt[p];
+        h.t[k] = nt_load(tt + p);
 #pragma unroll
-        for (int r = 0; r < R; ++r) h.r[k][r] = cache[(long long)r * n + p];
-        if constexpr (KIND == 1) h.w[k] = ww[p];
+        for (int r = 0; r < R; ++r) h.r[k][r] = nt_load(cache + (long long)r * n + p);
+        if constexpr (KIND == 1) h.w[k] = nt_load(ww + p);
       }
     };
     auto use_half = [&](const Half& h, const Tile& td, int part) {
