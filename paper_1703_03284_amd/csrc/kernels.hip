@@ -566,48 +566,68 @@ __device__ void run_qform(const Segment& sg, const Real* tab, double* bins, doub
   }
 }
 
-// One block per cell; thread k < K*K forms M[i][j] (i = k / K, j = k % K) over the cell's points.
+// One block per cell.  The cell's points are contiguous in the sorted arrays; they are taken in
+// chunks of kMomChunk: each thread loads one point and writes its K functions phi (complex FP64) to
+// LDS, then thread k < K*K forms M[i][j] (i = k / K, j = k % K) over the chunk from LDS, adding the
+// points in order.
+constexpr int kMomChunk = 256;
+
 template <typename Real, int R>
-__global__ __launch_bounds__(256) void k_moments(Segment sg, const Tile* __restrict__ cells, double* __restrict__ mom) {
+__global__ __launch_bounds__(kMomChunk) void k_moments(Segment sg, const Tile* __restrict__ cells,
+                                                       double* __restrict__ mom) {
   constexpr int K = 8 + R;
+  static_assert(K * K <= kMomChunk, "one thread per moment");
   using V2 = typename Ops<Real>::V2;
+  __shared__ double2 phi[kMomChunk * K];
+  __shared__ double pw[kMomChunk];
   const Tile cell = cells[blockIdx.x];
-  const int k = threadIdx.x;
-  if (k >= K * K) return;
-  const int i = k / K, j = k % K;
+  const Tile first = sg.tiles[cell.start], last = sg.tiles[cell.start + cell.count - 1];
+  const long long p0 = first.start, p1 = (long long)last.start + last.count;
   const V2* __restrict__ tt = (const V2*)sg.tt;
   const Real* __restrict__ ww = (const Real*)sg.w;
   const V2* __restrict__ cache = (const V2*)sg.cache;
-  auto phi = [&](int q, long long p, double t12, double t13, double& re, double& im) {
-    im = 0.0;
-    if (q < 4) {
-      re = q == 0 ? 1.0 : q == 1 ? t12 : q == 2 ? t12 * t12 : t12 * t12 * t12;
-    } else if (q < 8) {
-      re = q == 4 ? 1.0 : q == 5 ? t13 : q == 6 ? t13 * t13 : t13 * t13 * t13;
-    } else {
-      const V2 c = cache[(long long)(q - 8) * sg.n + p];
-      re = (double)c.x;
-      im = (double)c.y;
-    }
-  };
+  const int k = threadIdx.x;
+  const int i = k / K, j = k % K;
   double sr = 0.0, si = 0.0;
-  for (int t = cell.start; t < cell.start + cell.count; ++t) {
-    const Tile td = sg.tiles[t];
-    for (int q = 0; q < td.count; ++q) {
-      const long long p = (long long)td.start + q;
+  for (long long c0 = p0; c0 < p1; c0 += kMomChunk) {
+    const int m = (int)min((long long)kMomChunk, p1 - c0);
+    __syncthreads();  // the previous chunk is consumed
+    if (k < m) {
+      const long long p = c0 + k;
       const V2 x = tt[p];
-      const double w = (double)ww[p];
-      double ar, ai, br, bi;
-      phi(i, p, (double)x.x, (double)x.y, ar, ai);
-      phi(j, p, (double)x.x, (double)x.y, br, bi);
+      const double t12 = (double)x.x, t13 = (double)x.y;
+      double2* f = phi + k * K;
+      f[0] = double2{1.0, 0.0};
+      f[1] = double2{t12, 0.0};
+      f[2] = double2{t12 * t12, 0.0};
+      f[3] = double2{t12 * t12 * t12, 0.0};
+      f[4] = double2{1.0, 0.0};
+      f[5] = double2{t13, 0.0};
+      f[6] = double2{t13 * t13, 0.0};
+      f[7] = double2{t13 * t13 * t13, 0.0};
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const V2 c = cache[(long long)r * sg.n + p];
+        f[8 + r] = double2{(double)c.x, (double)c.y};
+      }
+      pw[k] = (double)ww[p];
+    }
+    __syncthreads();
+    if (k < K * K) {
       // w phi_i conj(phi_j)
-      sr += w * (ar * br + ai * bi);
-      si += w * (ai * br - ar * bi);
+      for (int q = 0; q < m; ++q) {
+        const double2 a = phi[q * K + i], b = phi[q * K + j];
+        const double w = pw[q];
+        sr += w * (a.x * b.x + a.y * b.y);
+        si += w * (a.y * b.x - a.x * b.y);
+      }
     }
   }
-  double* out = mom + ((long long)blockIdx.x * K * K + k) * 2;
-  out[0] = sr;
-  out[1] = si;
+  if (k < K * K) {
+    double* out = mom + ((long long)blockIdx.x * K * K + k) * 2;
+    out[0] = sr;
+    out[1] = si;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1269,11 +1289,11 @@ hipError_t launch_upload(void* d_dst, const void* h_src_dev, size_t bytes, hipSt
 template <typename Real>
 hipError_t moments_impl(int R, const Segment* s, const Tile* cells, int n_cells, double* mom, hipStream_t st) {
   switch (R) {
-    case 0: k_moments<Real, 0><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
-    case 1: k_moments<Real, 1><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
-    case 2: k_moments<Real, 2><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
-    case 3: k_moments<Real, 3><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
-    case 4: k_moments<Real, 4><<<n_cells, 256, 0, st>>>(*s, cells, mom); break;
+    case 0: k_moments<Real, 0><<<n_cells, kMomChunk, 0, st>>>(*s, cells, mom); break;
+    case 1: k_moments<Real, 1><<<n_cells, kMomChunk, 0, st>>>(*s, cells, mom); break;
+    case 2: k_moments<Real, 2><<<n_cells, kMomChunk, 0, st>>>(*s, cells, mom); break;
+    case 3: k_moments<Real, 3><<<n_cells, kMomChunk, 0, st>>>(*s, cells, mom); break;
+    case 4: k_moments<Real, 4><<<n_cells, kMomChunk, 0, st>>>(*s, cells, mom); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

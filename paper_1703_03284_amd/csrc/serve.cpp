@@ -13,6 +13,7 @@
 // runs join the next step.  A job's block count depends only on its own sizes, so its reduction
 // order, and therefore its result, is bitwise the same alone or in any mix.
 #include <hip/hip_runtime.h>
+#include <immintrin.h>
 
 #include <algorithm>
 #include <atomic>
@@ -42,10 +43,16 @@ using Clock = std::chrono::steady_clock;
 namespace {
 
 constexpr int kServeWaves = 4;
+constexpr int kServeTilesPerWave = 8;
 constexpr int kMaxSegBlocks = 512;
+constexpr int kBatchWindowUs = 100;
+constexpr size_t kBatchBytes0 = (size_t)4 << 20;   // initial step descriptor buffer (host and device)
+constexpr size_t kResultBytes0 = (size_t)1 << 20;  // initial result buffer (mapped host memory)
 
+// blocks of a job's event segment: about kServeTilesPerWave tiles per wave
 int seg_blocks(int n_tiles) {
-  const int b = (n_tiles + 2 * kServeWaves - 1) / (2 * kServeWaves);
+  const int per_block = kServeTilesPerWave * kServeWaves;
+  const int b = (n_tiles + per_block - 1) / per_block;
   return std::min(std::max(b, 1), kMaxSegBlocks);
 }
 
@@ -81,15 +88,18 @@ struct SJob {
   size_t bytes = 0;
   JobState state = QUEUED;
   int status = MIPWA_OK;
-  bool cancel = false;
+  std::atomic<bool> cancel{false};
   std::string err;
   Clock::time_point t_submit, t_done;
   std::thread worker;
-  // one outstanding evaluation request
+  // One outstanding evaluation request.  req and inflight are guarded by the server's mutex (the
+  // scheduler forms batches under it); done, and the hand-over of staged and of the results, by the
+  // job's own mutex m, so that returning the results of a step takes no server-wide lock.
   bool req = false, inflight = false, done = false;
   std::vector<char> staged;  // [Real table | pad to 256 | theta (P doubles)]
   double f = 0;
   std::vector<double> g;
+  std::mutex m;
   std::condition_variable cv;
   FitOut result;
 };
@@ -149,7 +159,7 @@ struct mipwa_server {
   std::mutex norm_mu;  // creation of shared normalisation sets
   std::condition_variable cv_sched, cv_done;
   std::thread sched;
-  bool stop = false;
+  std::atomic<bool> stop{false};
   std::vector<double> n12, n13, nw;
   std::vector<std::unique_ptr<NormSet>> norms;
   std::map<int64_t, std::unique_ptr<SJob>> jobs;
@@ -157,8 +167,12 @@ struct mipwa_server {
   int64_t next_id = 1;
   size_t used = 0, peak = 0;
   int running = 0;  // LOADING + ACTIVE
+  int n_active = 0;  // ACTIVE: jobs that ask for evaluations
+  int n_req = 0;     // ACTIVE jobs with a request not yet taken into a batch
   long long steps = 0;
   double batch_sum = 0;
+  // scheduler time (s): idle until a request, in the batching window, staging the step, on the GPU
+  double t_idle = 0, t_window = 0, t_stage = 0, t_gpu = 0;
   bool any_submit = false;
   Clock::time_point t_first_submit, t_last_done, t_create = Clock::now();
   std::vector<double> latencies;
@@ -192,6 +206,12 @@ void trace(const mipwa_server* S, const char* fmt, ...) {
   std::vsnprintf(msg, sizeof msg, fmt, ap);
   va_end(ap);
   std::fprintf(stderr, "[serve %.4f] %s\n", std::chrono::duration<double>(Clock::now() - S->t_create).count(), msg);
+}
+
+// Wake a job's worker after setting one of the flags its wait checks (cancel, stop or done).
+void wake(SJob* J) {
+  { std::lock_guard<std::mutex> jl(J->m); }
+  J->cv.notify_all();
 }
 
 void admit(mipwa_server* S) {
@@ -240,7 +260,20 @@ NormSet* get_norm(mipwa_server* S, const ModelHost& mh, hipStream_t st, std::str
 }
 
 void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
+  // no step uses the job's buffers any more; freeing device memory waits for the device, so it
+  // happens before the server's lock is taken
+  J->ev = PointSet();
+  J->d_rec.release();
+  J->d_grec.release();
+  J->d_consts.release();
+  J->d_ncache.release();
+  J->d_mom.release();
   std::lock_guard<std::mutex> lk(S->mu);
+  if (J->state == ACTIVE) S->n_active -= 1;
+  if (J->req) {
+    J->req = false;
+    S->n_req -= 1;
+  }
   J->state = FINISHED;
   J->status = status;
   J->err = err;
@@ -250,12 +283,6 @@ void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
     S->latencies.push_back(std::chrono::duration<double>(J->t_done - J->t_submit).count());
     S->t_last_done = J->t_done;
   }
-  J->ev = PointSet();
-  J->d_rec.release();
-  J->d_grec.release();
-  J->d_consts.release();
-  J->d_ncache.release();
-  J->d_mom.release();
   S->used -= J->bytes;
   S->running -= 1;
   S->cv_done.notify_all();
@@ -335,6 +362,7 @@ static void serve_worker(mipwa_server* S, SJob* J) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     J->state = ACTIVE;
+    S->n_active += 1;
     trace(S, "job %lld active", (long long)J->id);
     S->cv_sched.notify_all();
   }
@@ -347,14 +375,38 @@ static void serve_worker(mipwa_server* S, SJob* J) {
     }
     std::vector<char> staged;
     stage(mh, S->fp64, th, staged);
-    std::unique_lock<std::mutex> lk(S->mu);
     if (J->cancel || S->stop) return MIPWA_E_CANCELLED;
-    J->staged.swap(staged);
-    J->req = true;
-    J->done = false;
-    S->cv_sched.notify_all();
-    J->cv.wait(lk, [&] { return J->done || ((J->cancel || S->stop) && !J->inflight); });
-    if (!J->done) return MIPWA_E_CANCELLED;
+    {
+      std::lock_guard<std::mutex> jl(J->m);
+      J->staged.swap(staged);
+      J->done = false;
+    }
+    {
+      // the scheduler is woken by the first request of a step and by the one that completes it
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->stop) return MIPWA_E_CANCELLED;
+      J->req = true;
+      S->n_req += 1;
+      if (S->n_req == 1 || S->n_req >= S->n_active) S->cv_sched.notify_one();
+    }
+    std::unique_lock<std::mutex> jl(J->m);
+    J->cv.wait(jl, [&] { return J->done || J->cancel || S->stop; });
+    if (!J->done) {
+      // cancelled: withdraw the request unless a step has taken it, else wait for that step
+      jl.unlock();
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (!J->inflight) {
+          if (J->req) {
+            J->req = false;
+            S->n_req -= 1;
+          }
+          return MIPWA_E_CANCELLED;
+        }
+      }
+      jl.lock();
+      J->cv.wait(jl, [&] { return J->done; });
+    }
     f = std::isfinite(J->f) ? J->f : INFINITY;
     std::copy(J->g.begin(), J->g.end(), g);
     return MIPWA_OK;
@@ -425,8 +477,13 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
       o_th[j] = o_tab[j] + toff;
       max_nint = std::max(max_nint, js[j]->mh.N - 1);
     }
-    if (S->h_batch.alloc(off, true) != hipSuccess || S->d_batch.alloc(off) != hipSuccess)
-      return S->fail(MIPWA_E_NOMEM, "batch buffer allocation failed");
+    // grown geometrically: batches grow step by step while jobs become active, and each
+    // reallocation of pinned or device memory costs milliseconds (a device free synchronises)
+    if (off > S->h_batch.bytes || off > S->d_batch.bytes) {
+      const size_t cap = std::max(off, 2 * std::max(S->h_batch.bytes, S->d_batch.bytes));
+      if (S->h_batch.alloc(cap, true) != hipSuccess || S->d_batch.alloc(cap) != hipSuccess)
+        return S->fail(MIPWA_E_NOMEM, "batch buffer allocation failed");
+    }
     char* hb = S->h_batch.as<char>();
     char* db = S->d_batch.as<char>();
     std::memcpy(hb + o_map, map.data(), map.size() * sizeof(int2));
@@ -490,7 +547,13 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
     if (launch_reduce(reinterpret_cast<const Segment*>(db + o_seg), reinterpret_cast<const Job*>(db + o_job),
                       reinterpret_cast<const int2*>(db + o_task), (int)tasks.size(), nj, nullptr, S->stream) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batched reduction kernels failed");
-    if (hipStreamSynchronize(S->stream) != hipSuccess) return S->fail(MIPWA_E_HIP, "batch sync failed");
+    const auto t_l = Clock::now();
+    // spin on the stream (the scheduler has nothing else to do meanwhile): a blocking wait wakes up
+    // late while the host is busy with the jobs' threads
+    hipError_t q;
+    while ((q = hipStreamQuery(S->stream)) == hipErrorNotReady) _mm_pause();
+    if (q != hipSuccess) return S->fail(MIPWA_E_HIP, std::string("batch failed: ") + hipGetErrorString(q));
+    S->t_gpu += std::chrono::duration<double>(Clock::now() - t_l).count();
   }
   const double* res = S->h_res.as<double>();
   for (SJob* J : batch) {
@@ -506,16 +569,6 @@ void sched_loop(mipwa_server* S) {
   std::unique_lock<std::mutex> lk(S->mu);
   while (!S->stop) {
     admit(S);
-    auto n_pending = [&] {
-      int p = 0, a = 0;
-      for (auto& kv : S->jobs) {
-        SJob* J = kv.second.get();
-        if (J->state != ACTIVE) continue;
-        ++a;
-        if (J->req && !J->inflight && !J->cancel) ++p;
-      }
-      return std::make_pair(p, a);
-    };
     for (auto& kv : S->jobs)
       if (kv.second->state == FINISHED && kv.second->worker.joinable()) kv.second->worker.join();
     auto admissible = [&] {
@@ -523,40 +576,50 @@ void sched_loop(mipwa_server* S) {
       SJob* J = S->queue.front();
       return J->cancel || S->running == 0 || S->used + J->bytes <= S->budget;
     };
-    S->cv_sched.wait(lk, [&] { return S->stop || n_pending().first > 0 || admissible(); });
+    const auto t_a = Clock::now();
+    S->cv_sched.wait(lk, [&] { return S->stop || S->n_req > 0 || admissible(); });
     if (S->stop) break;
-    if (n_pending().first == 0) continue;
-    if (S->stop) break;
-    // batching window: until every active job has asked, or 2 ms after the first request
-    const auto deadline = Clock::now() + std::chrono::milliseconds(2);
-    while (!S->stop) {
-      auto pa = n_pending();
-      if (pa.first >= pa.second) break;
+    if (S->n_req == 0) continue;
+    // batching window: until every active job has asked, or kBatchWindowUs after the first request
+    const auto t_b = Clock::now();
+    const auto deadline = t_b + std::chrono::microseconds(kBatchWindowUs);
+    while (!S->stop && S->n_req < S->n_active)
       if (S->cv_sched.wait_until(lk, deadline) == std::cv_status::timeout) break;
-    }
     if (S->stop) break;
+    const auto t_c = Clock::now();
+    S->t_idle += std::chrono::duration<double>(t_b - t_a).count();
+    S->t_window += std::chrono::duration<double>(t_c - t_b).count();
     std::vector<SJob*> batch;
     for (auto& kv : S->jobs) {
       SJob* J = kv.second.get();
-      if (J->state == ACTIVE && J->req && !J->inflight && !J->cancel) {
-        J->inflight = true;
-        batch.push_back(J);
-      }
+      if (J->state != ACTIVE || !J->req || J->inflight) continue;
+      J->req = false;
+      S->n_req -= 1;
+      if (J->cancel) continue;  // its worker withdraws
+      J->inflight = true;
+      batch.push_back(J);
     }
     if (batch.empty()) continue;
     lk.unlock();
+    const double gpu0 = S->t_gpu;
+    const auto t_d = Clock::now();
     const int rc = run_batch(S, batch);
+    S->t_stage += std::chrono::duration<double>(Clock::now() - t_d).count() - (S->t_gpu - gpu0);
     lk.lock();
-    for (SJob* J : batch) {
-      if (rc) J->f = NAN;
-      J->req = false;
-      J->inflight = false;
-      J->done = true;
-      J->cv.notify_all();
-    }
+    for (SJob* J : batch) J->inflight = false;
     S->steps += 1;
     S->batch_sum += (double)batch.size();
-    if (S->steps % 256 == 1) trace(S, "step %lld: batch %zu of %d active", S->steps, batch.size(), n_pending().second);
+    lk.unlock();
+    for (SJob* J : batch) {
+      {
+        std::lock_guard<std::mutex> jl(J->m);
+        if (rc) J->f = NAN;
+        J->done = true;
+      }
+      J->cv.notify_one();
+    }
+    lk.lock();
+    if (S->steps % 256 == 1) trace(S, "step %lld: batch %zu of %d active", S->steps, batch.size(), S->n_active);
   }
 }
 
@@ -580,6 +643,15 @@ int mipwa_server_create(int device, int precision, size_t budget, mipwa_server**
   if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
     delete S;
     return MIPWA_E_HIP;
+  }
+  // step buffers sized up front for a few hundred jobs per step: allocating pinned or device memory
+  // during the steps costs milliseconds each time (they still grow if a step needs more)
+  if (S->h_batch.alloc(kBatchBytes0, true) != hipSuccess || S->d_batch.alloc(kBatchBytes0) != hipSuccess ||
+      S->h_res.alloc(kResultBytes0, true) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&S->h_res_dev, S->h_res.p, 0) != hipSuccess) {
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+    return MIPWA_E_NOMEM;
   }
   S->sched = std::thread(sched_loop, S);
   *out = S;
@@ -693,7 +765,7 @@ int mipwa_server_cancel(mipwa_server* S, int64_t id) {
   if (it == S->jobs.end()) return S->fail(MIPWA_E_INVAL, "unknown job");
   SJob* J = it->second.get();
   J->cancel = true;
-  J->cv.notify_all();
+  wake(J);
   S->cv_sched.notify_all();
   return MIPWA_OK;
 }
@@ -735,13 +807,15 @@ void mipwa_server_destroy(mipwa_server* S) {
     S->stop = true;
     for (auto& kv : S->jobs) {
       kv.second->cancel = true;
-      kv.second->cv.notify_all();
+      wake(kv.second.get());
     }
     S->cv_sched.notify_all();
   }
   if (S->sched.joinable()) S->sched.join();
   for (auto& kv : S->jobs)
     if (kv.second->worker.joinable()) kv.second->worker.join();
+  trace(S, "scheduler: %lld steps; idle %.3f s, batching window %.3f s, staging %.3f s, launch to results %.3f s",
+        S->steps, S->t_idle, S->t_window, S->t_stage, S->t_gpu);
   (void)hipSetDevice(S->device);
   (void)hipStreamSynchronize(S->stream);
   S->jobs.clear();
