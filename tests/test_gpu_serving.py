@@ -115,3 +115,28 @@ def test_invalid_submissions_are_rejected(norm, jobs):
             srv.submit(wl.decay, kn, wl.resonances, s12, s13, bad)
         ok = srv.wait(_submit(srv, jobs["C"]))
         assert ok["status"] == 0
+
+
+def test_cancellation_at_any_point_and_teardown_with_work_in_flight(norm, jobs):
+    """Many jobs, cancelled at staggered times (queued, loading, between steps or inside one), then
+    the server closed while the rest are still running: every wait returns, the cancelled ones as
+    E_CANCELLED, the others converged or cancelled by the teardown, and an untouched job's result is
+    the one it gets alone."""
+    import time
+    with _server(norm, "mixed") as ref_srv:
+        ref = ref_srv.wait(_submit(ref_srv, jobs["D"]))
+    srv = _server(norm, "mixed")
+    keys = ["A", "B", "C"] * 8
+    ids = [_submit(srv, jobs[k]) for k in keys]
+    keep = _submit(srv, jobs["D"])
+    for k, j in enumerate(ids[::2]):
+        time.sleep(0.002 * (k % 4))
+        srv.cancel(j)
+    res_keep = srv.wait(keep)
+    assert res_keep["status"] == 0
+    assert np.array_equal(res_keep["theta"], ref["theta"])
+    for j in ids[::2]:
+        assert srv.wait(j)["status"] in (-7, 0, -6)  # a job may finish before its cancel lands
+    for k in ("A", "B"):
+        _submit(srv, jobs[k])
+    srv.close()  # jobs still queued or running are cancelled; nothing hangs or faults
