@@ -55,19 +55,50 @@ struct Ops<double> {
   }
 };
 
+// Pointers into device memory that the compiler may treat as global (not generic) addresses: loads
+// then take a wave-uniform base in scalar registers plus a 32-bit lane offset.
+#define MIPWA_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const MIPWA_GLOBAL T* global_ptr(const T* p) {
+  return (const MIPWA_GLOBAL T*)p;
+}
+
 // Streaming load that marks its lines as not worth keeping in the caches (each point is read once per
 // evaluation, and a point set is larger than the caches).
 template <typename T>
-__device__ __forceinline__ T nt_load(const T* p) {
+__device__ __forceinline__ T nt_load(const MIPWA_GLOBAL T* p) {
   static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "4-, 8- or 16-byte element");
   if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_nontemporal_load((const unsigned*)p));
+    return __builtin_bit_cast(T, __builtin_nontemporal_load((const MIPWA_GLOBAL unsigned*)p));
   } else if constexpr (sizeof(T) == 8) {
-    return __builtin_bit_cast(T, __builtin_nontemporal_load((const unsigned long long*)p));
+    return __builtin_bit_cast(T, __builtin_nontemporal_load((const MIPWA_GLOBAL unsigned long long*)p));
   } else {
     using U4v = unsigned __attribute__((ext_vector_type(4)));
-    return __builtin_bit_cast(T, __builtin_nontemporal_load((const U4v*)p));
+    return __builtin_bit_cast(T, __builtin_nontemporal_load((const MIPWA_GLOBAL U4v*)p));
   }
+}
+
+// A pointer or count that is the same for the whole wave, held in scalar registers.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ long long uniform_ll(long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Tile descriptors through the constant address space, so that a wave-uniform index becomes a scalar load.
+using ConstTiles = const __attribute__((address_space(4))) Tile*;
+
+__device__ __forceinline__ Tile load_tile(ConstTiles tiles, int i) {
+  return Tile{tiles[i].j12, tiles[i].j13, tiles[i].start, tiles[i].count};
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -183,11 +214,11 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     cre[r] = O::uniform(cv[2 * r]);
     cim[r] = O::uniform(cv[2 * r + 1]);
   }
-  const V2* __restrict__ tt = (const V2*)sg.tt;
-  const double2* __restrict__ ss = (const double2*)sg.ss;
-  const Real* __restrict__ ww = (const Real*)sg.w;
-  const V2* __restrict__ cache = (const V2*)sg.cache;
-  const long long n = sg.n;
+  const V2* __restrict__ tt = uniform_ptr((const V2*)sg.tt);
+  const double2* __restrict__ ss = uniform_ptr((const double2*)sg.ss);
+  const Real* __restrict__ ww = uniform_ptr((const Real*)sg.w);
+  const V2* __restrict__ cache = uniform_ptr((const V2*)sg.cache);
+  const long long n = uniform_ll(sg.n);
 
   const long long nw = (long long)sg.n_blocks * waves;
   const long long gw = (long long)local_block * waves + wave;
@@ -347,15 +378,20 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
       V2 r[HB][R1];
       Real w[HB];
     };
+    // the tile's base addresses are wave-uniform (scalar registers); lanes add a 32-bit offset
     auto load_half = [&](Half& h, const Tile& td, int part) {
+      const MIPWA_GLOBAL V2* tb = global_ptr(tt + td.start);
+      const MIPWA_GLOBAL Real* wb = global_ptr(ww + td.start);
 #pragma unroll
       for (int k = 0; k < HB; ++k) {
         const int i = (part * HB + k) * 64 + lane;
-        const long long p = (long long)td.start + (i < td.count ? i : td.count - 1);
-        h.t[k] = nt_load(tt + p);
+        // offset within the tile (count >= 1), bounded so that it fits a 32-bit lane offset
+        static_assert((kTile & (kTile - 1)) == 0, "the tile size is a power of two");
+        const unsigned j = (unsigned)(i < td.count ? i : td.count - 1) & (unsigned)(kTile - 1);
+        h.t[k] = nt_load(tb + j);
 #pragma unroll
-        for (int r = 0; r < R; ++r) h.r[k][r] = nt_load(cache + (long long)r * n + p);
-        if constexpr (KIND == 1) h.w[k] = nt_load(ww + p);
+        for (int r = 0; r < R; ++r) h.r[k][r] = nt_load(global_ptr(cache + ((long long)r * n + td.start)) + j);
+        if constexpr (KIND == 1) h.w[k] = nt_load(wb + j);
       }
     };
     auto use_half = [&](const Half& h, const Tile& td, int part) {
@@ -374,12 +410,13 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     };
     if (t0 < t1) {
       Half a, b;
-      Tile td = sg.tiles[t0];
+      const ConstTiles tiles = (ConstTiles)uniform_ptr(sg.tiles);
+      Tile td = load_tile(tiles, t0);
       load_half(a, td, 0);
 #pragma unroll 1
       for (int ti = t0; ti < t1; ++ti) {
         // the next descriptor (clamped to this wave's last tile) is requested a tile ahead
-        const Tile tn = sg.tiles[min(ti + 1, t1 - 1)];
+        const Tile tn = load_tile(tiles, min(ti + 1, t1 - 1));
         load_half(b, td, 1);
         enter_cell(td.j12, td.j13);
         use_half(a, td, 0);
