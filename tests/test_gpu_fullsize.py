@@ -1,9 +1,10 @@
 """Checks at the benchmark workloads' full sizes, in the launch configuration bench.py times.
 
-The oracle computes -2 ln L at 10M + 10M points and the gradient at 1M + 2M points; at 5M + 5M with
-masses and widths floated (where the oracle's per-point five-point differences would take minutes)
-the checks are properties that hold at any size: the FP64 adjoint against central differences of
-the library's FP64 -2 ln L, and the mixed-precision gradient against the FP64 one.
+The oracle computes -2 ln L and the knot and coefficient gradient at 10M + 10M points and at 1M + 2M
+points; at 5M + 5M with masses and widths floated (where the oracle's per-point five-point
+differences would take minutes) the checks are properties that hold at any size: the FP64 adjoint
+against central differences of the library's FP64 -2 ln L, and the mixed-precision gradient against
+the FP64 one.
 """
 import numpy as np
 import pytest
@@ -34,14 +35,14 @@ def headline():
     e_ev = L.hist_lookup(table, d.smin, d.smax, *ev)
     e_nm = L.hist_lookup(table, d.smin, d.smax, s12, s13)
     th = wl.start()
-    v_o = L.nll(m, th, ev, (s12, s13, w * e_nm), float(np.sum(np.log(e_ev))))
-    return wl, table, ev, (s12, s13, w), th, v_o
+    v_o, g_o = L.nll_and_grad(m, th, ev, (s12, s13, w * e_nm), float(np.sum(np.log(e_ev))), shapes=False)
+    return wl, table, ev, (s12, s13, w), th, v_o, g_o
 
 
 @pytest.mark.parametrize("prec,tol", [("mixed", 1e-6), ("fp64", 1e-10)])
 def test_headline_nll_full_size(headline, prec, tol):
     from paper_1703_03284_amd import context_for
-    wl, table, ev, nm, th, v_o = headline
+    wl, table, ev, nm, th, v_o, g_o = headline
     d = wl.decay
     ctx = context_for(d, wl.knots(), wl.resonances, _prec(prec))
     ctx.set_eff_table(table, d.smin, d.smax)
@@ -49,12 +50,17 @@ def test_headline_nll_full_size(headline, prec, tol):
     ctx.load_norm(*nm)
     v, g = ctx.eval(th)
     assert rel(v, v_o) <= tol, (v, v_o)
+    # the gradient of the knots and coefficients against the oracle's (shapes fixed: their partials are 0)
+    n_ck = 2 * wl.n_knots + 2 * wl.n_res
+    g_tol = 1e-8 if prec == "fp64" else 1e-4
+    assert np.abs(g[:n_ck] - g_o[:n_ck]).max() <= g_tol * np.abs(g_o[:n_ck]).max()
+    assert np.all(g[n_ck:] == 0.0)
     ctx.close()
 
 
 def test_headline_mixed_gradient_vs_fp64_full_size(headline):
     from paper_1703_03284_amd import context_for
-    wl, table, ev, nm, th, _ = headline
+    wl, table, ev, nm, th, _, _ = headline
     d = wl.decay
     out = {}
     for prec in ("fp64", "mixed"):
