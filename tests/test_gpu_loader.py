@@ -107,3 +107,28 @@ def test_reloading_replaces_the_points():
 def _fp64():
     from paper_1703_03284_amd import FP64
     return FP64
+
+
+def test_region_tolerance_at_the_boundary():
+    """Points within 1e-9 s_max of the Dalitz boundary are accepted (rounding of the caller's
+    kinematics), points beyond it are rejected with the first offending index."""
+    from oracle import kinematics as K
+    from tests.conftest import oracle_model
+    wl = synth.C1
+    m = oracle_model(wl)
+    tol = 1e-9 * K.smax(m)
+    s12 = np.array([0.5, 1.0, 1.7, 2.2])
+    lo, hi = K.s13_limits(m, s12)
+    ctx = _ctx(wl)
+    # just inside the tolerance band on both sides of the s13 range, and at the s12 ends
+    a = np.concatenate([s12, s12, [K.smin(m) - 0.5 * tol]])
+    b = np.concatenate([hi + 0.5 * tol, lo - 0.5 * tol, [K.s13_limits(m, np.array([K.smin(m)]))[0][0]]])
+    ctx.load_events(a, b)
+    # beyond the band: rejected
+    b2 = b.copy()
+    b2[2] = hi[2] + 3.0 * tol
+    _raises(lambda: ctx.load_events(a, b2), -1, "point 2 ")
+    a3 = a.copy()
+    a3[-1] = K.smin(m) - 3.0 * tol
+    _raises(lambda: ctx.load_events(a3, b), -1, "point 8 ")
+    ctx.close()
