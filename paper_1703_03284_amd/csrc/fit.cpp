@@ -48,9 +48,18 @@ void matvec(const std::vector<double>& B, const std::vector<double>& x, std::vec
   const size_t n = x.size();
   y.assign(n, 0.0);
   for (size_t i = 0; i < n; ++i) {
-    double s = 0.0;
-    for (size_t j = 0; j < n; ++j) s += B[i * n + j] * x[j];
-    y[i] = s;
+    // four partial sums: independent chains the compiler can keep in vector registers
+    const double* Bi = B.data() + i * n;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    size_t j = 0;
+    for (; j + 4 <= n; j += 4) {
+      s0 += Bi[j] * x[j];
+      s1 += Bi[j + 1] * x[j + 1];
+      s2 += Bi[j + 2] * x[j + 2];
+      s3 += Bi[j + 3] * x[j + 3];
+    }
+    for (; j < n; ++j) s0 += Bi[j] * x[j];
+    y[i] = (s0 + s1) + (s2 + s3);
   }
 }
 
@@ -262,10 +271,19 @@ int bfgs_fit(const FullEval& fg, int P, const std::vector<int>& polar_pairs, con
       std::vector<double> By;
       matvec(B, y, By);
       const double yBy = dot(y, By);
-      // B + (rho^2 y^T B y + rho) s s^T - rho (B y s^T + s y^T B)
-      for (size_t i = 0; i < n; ++i)
-        for (size_t j = 0; j < n; ++j)
-          B[i * n + j] += (rho * rho * yBy + rho) * s[i] * s[j] - rho * (By[i] * s[j] + s[i] * By[j]);
+      // B + (rho^2 y^T B y + rho) s s^T - rho (B y s^T + s y^T B), as B_ij += w_i s_j - s_i t_j with
+      // w = (rho^2 y^T B y + rho) s - rho B y and t = rho B y (two multiply-adds per element)
+      const double a = rho * rho * yBy + rho;
+      std::vector<double> w(n), t(n);
+      for (size_t i = 0; i < n; ++i) {
+        w[i] = a * s[i] - rho * By[i];
+        t[i] = rho * By[i];
+      }
+      for (size_t i = 0; i < n; ++i) {
+        const double wi = w[i], si = s[i];
+        double* Bi = B.data() + i * n;
+        for (size_t j = 0; j < n; ++j) Bi[j] += wi * s[j] - si * t[j];
+      }
     }
     x = lr.x;
     f = lr.f;
