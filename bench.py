@@ -319,6 +319,38 @@ def shapes_floated(steps, warmup, precision_name):
             "device_ms_per_step": r["dev_ms"], "stream_kernel_ms": r["stream_kernel_ms"]}
 
 
+def smaller_workloads(steps, warmup):
+    """The 10k-event fit workload (latency-bound: a few MB per evaluation) and the 1M-event FP64
+    workload with the polynomial efficiency per point (208 MB per evaluation, within the 256 MB
+    Infinity Cache), both in FP64 as their fits are."""
+    import synth
+    from paper_1703_03284_amd import FP64, context_for
+    out = []
+    for wl in (synth.C1, synth.C2):
+        d = wl.decay
+        pe = synth.PolyEfficiency.seeded(d, wl.seed("eff")) if wl.efficiency == "poly" else None
+        gen = context_for(d, wl.knots(), wl.resonances, FP64)
+        if pe is not None:
+            gen.set_eff_table(synth.efficiency_histogram(pe), d.smin, d.smax)
+        ev12, ev13, _ = gen.toy(wl.truth(), wl.n_events, wl.seed("events"))
+        gen.close()
+        n12, n13 = synth.uniform_phase_space(d, wl.n_norm, wl.seed("norm"))
+        w = np.full(wl.n_norm, synth.region_area_mc(d, 1 << 22, 5) / wl.n_norm)
+        events = (ev12, ev13) if pe is None else (ev12, ev13, pe(ev12, ev13))
+        norm = (n12, n13, w) if pe is None else (n12, n13, w, pe(n12, n13))
+        r = time_gpu(wl, FP64, None, events, norm, steps, warmup)
+        nbytes = wl.n_events * stream_bytes_per_point(8, wl.n_res, "data") + \
+            wl.n_norm * stream_bytes_per_point(8, wl.n_res, "norm")
+        out.append({"workload": f"D+->pi-pi+pi+ {wl.n_events} toy events + {wl.n_norm} uniform normalisation points, "
+                                f"{wl.n_knots} knots, {wl.n_res} resonances, efficiency {wl.efficiency}",
+                    "precision": "fp64", "value": r["value"], "unit": "evals/s", "ms_per_step": r["ms_per_step"],
+                    "device_ms_per_step": r["dev_ms"], "stream_kernel_ms": r["stream_kernel_ms"],
+                    "bytes_per_launch": nbytes,
+                    "achieved_GBs": nbytes / (r["stream_kernel_ms"] * 1e-3) / 1e9})
+        log(f"[bench] {out[-1]}")
+    return out
+
+
 def profile_pass(steps, which="headline"):
     """A few evaluations of one workload plus a 1 GiB device copy of known size (counter calibration)."""
     import torch
@@ -351,6 +383,7 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=256)
     ap.add_argument("--profile-pass", nargs="?", const="headline", choices=["headline", "shapes"])
     ap.add_argument("--no-shapes", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the likelihood would shard "
@@ -428,6 +461,8 @@ def main():
                                 "kernel_ms": sh["mixed"]["stream_kernel_ms"]}
         sh["fp64"]["mixed_speedup"] = sh["mixed"]["value"] / sh["fp64"]["value"]
         out["shapes_floated"] = sh
+    if not args.no_small:
+        out["smaller_workloads"] = smaller_workloads(args.steps, args.warmup)
     if not args.no_serve:
         out["serving"] = serving(args.serve_jobs, MIXED)
     if not args.no_paper_fit:
