@@ -228,10 +228,12 @@ int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves_per_block);
  * Dalitz-plot PDF) against one shared normalisation sample.  Jobs wait until their device footprint
  * fits the HBM budget, then load (cell sort and resonance cache on their own stream) and run the BFGS
  * fit of mipwa_fit in a worker thread.  Every evaluation a job needs is batched with the pending
- * evaluations of all other active jobs into a single launch of the streaming kernel; jobs admitted
- * while a step runs join the next one.  A job's result does not depend on which other jobs share
- * its steps (its kernel blocks and reduction order depend only on its own sizes).  Serving jobs keep
- * masses and widths fixed.  The server is thread-safe. */
+ * evaluations of all other active jobs into a single launch of the streaming kernel; a step starts
+ * once every active job has asked, or 100 us after the first request, and jobs admitted while a step
+ * runs join the next one.  A job's result does not depend on which other jobs share its steps (its
+ * kernel blocks and reduction order depend only on its own sizes).  Serving jobs keep masses and
+ * widths fixed.  The server is thread-safe.  With MIPWA_SERVE_TRACE set in the environment, admission,
+ * loading, completion and the scheduler's time split are printed to stderr. */
 typedef struct mipwa_server mipwa_server;
 typedef struct {
   double fits_per_s;   /* finished jobs / (last completion - first submission) */
