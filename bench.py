@@ -297,7 +297,7 @@ def otf_ops_per_point(spins, kind):
     return ops, trans
 
 
-# The vector ALU ceiling without packed FP32 math (which this build leaves off): 256 CUs x 4 SIMDs x
+# The vector ALU ceiling without packed FP32 math (the library is compiled without it): 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz lane-operations per second; a transcendental takes four operation slots.
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 TRANS_SLOTS = 4
@@ -386,7 +386,7 @@ def main():
     ap.add_argument("--no-small", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the likelihood would shard "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the likelihood would shard "
               "by points with one small all-reduce per evaluation).", file=sys.stderr)
         sys.exit(2)
     if args.profile_pass:
