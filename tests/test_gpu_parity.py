@@ -97,6 +97,43 @@ def test_mass_and_width_gradient(prec):
     _check(prob, ctx, *tol, shapes=True)
 
 
+# the largest model the library takes: 128 knots and 4 resonances (one of them spin 0); its
+# per-evaluation table no longer fits the kernel arguments in either precision
+MAX_MODEL = synth.Workload("max_model", 9, "fp64", 2000, 12000, 128,
+                           (synth.RHO770, synth.F2_1270, synth.RHO1450, synth.F0_980), "poly", float_shapes=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shapes", [False, True])
+def test_largest_model(prec, shapes):
+    prob = make_problem(MAX_MODEL, MAX_MODEL.n_events, MAX_MODEL.n_norm, seed=9)
+    ctx = prob.context(_prec(prec))
+    if shapes:
+        ctx.set_fixed(MAX_MODEL.fixed())
+        tol = (FP64_NLL, 1e-7) if prec == "fp64" else (MIX_NLL, MIX_G)
+    else:
+        tol = (FP64_NLL, FP64_G) if prec == "fp64" else (MIX_NLL, MIX_G)
+    _check(prob, ctx, *tol, shapes=shapes)
+
+
+def test_empty_and_oversized_inputs_are_rejected():
+    from paper_1703_03284_amd import MipwaError, context_for
+    wl = synth.C1
+    ctx = context_for(wl.decay, wl.knots(), wl.resonances)
+    for call in (lambda: ctx.load_events(np.array([]), np.array([])),
+                 lambda: ctx.load_norm(np.array([]), np.array([]), np.array([]))):
+        with pytest.raises(MipwaError) as e:
+            call()
+        assert e.value.status == -1
+    ctx.close()
+    with pytest.raises(MipwaError) as e:
+        context_for(wl.decay, synth.uniform_knots(wl.decay, 129), wl.resonances)
+    assert e.value.status == -1
+    with pytest.raises(MipwaError) as e:
+        context_for(wl.decay, wl.knots(), wl.resonances + (synth.RHO1450, synth.F0_980, synth.F0_1370))
+    assert e.value.status == -1
+
+
 def test_mass_width_gradient_vs_finite_differences():
     """FP64 analytic adjoint vs central differences (h = 1e-6) of the library's own FP64 -2 ln L."""
     wl = synth.C4
