@@ -116,6 +116,26 @@ def test_largest_model(prec, shapes):
     _check(prob, ctx, *tol, shapes=shapes)
 
 
+# a spline S-wave alone (no resonances): the whole amplitude is the spline
+SWAVE_ONLY = synth.Workload("swave_only", 10, "fp64", 3000, 20000, 30, (), "flat")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_spline_swave_without_resonances(prec):
+    prob = make_problem(SWAVE_ONLY, SWAVE_ONLY.n_events, SWAVE_ONLY.n_norm, seed=10)
+    ctx = prob.context(_prec(prec))
+    tol = (FP64_NLL, FP64_G) if prec == "fp64" else (MIX_NLL, MIX_G)
+    _check(prob, ctx, *tol)
+    # the constant S-wave (every knot 1, phase 0) has |A|^2 = 4 everywhere: -2 ln L = 2 n ln(sum w)
+    th = np.zeros(2 * SWAVE_ONLY.n_knots)
+    th[0::2] = 1.0
+    v, _ = ctx.eval(th)
+    n = SWAVE_ONLY.n_events
+    expect = -2.0 * n * np.log(4.0) + 2.0 * n * np.log(4.0 * np.sum(prob.norm[2]))
+    assert abs(v - expect) <= (1e-10 if prec == "fp64" else 1e-6) * abs(expect) + 1e-9 * n, (v, expect)
+    ctx.close()
+
+
 def test_empty_and_oversized_inputs_are_rejected():
     from paper_1703_03284_amd import MipwaError, context_for
     wl = synth.C1
