@@ -121,12 +121,21 @@ template <typename Real, int R, bool DER>
 __device__ __forceinline__ void bw_pairing(const Kin<Real>& k, const Real* __restrict__ res, Real x, Real y,
                                            Real* br, Real* bi, Real* er, Real* ei, Real* fr, Real* fi) {
   using O = Ops<Real>;
-  const Real ix = O::rcp(x);
+  // FP32: one reciprocal square root gives both 1/x and sqrt(x) (a quarter-rate operation fewer);
+  // FP64 keeps the correctly rounded division and root
+  Real ix, sx, isx = Real(0);
+  if constexpr (sizeof(Real) == 4) {
+    isx = O::rsqrt(x);
+    sx = x * isx;
+    ix = isx * isx;
+  } else {
+    ix = O::rcp(x);
+    sx = O::sqrt(x);
+  }
   Real q2 = (x - k.thr_hi) * (x - k.thr_lo) * (Real(0.25) * ix);
   Real p2 = (x - k.pb_hi) * (x - k.pb_lo) * (Real(0.25) * ix);
   q2 = q2 > Real(0) ? q2 : Real(0);
   p2 = p2 > Real(0) ? p2 : Real(0);
-  const Real sx = O::sqrt(x);
   const Real q = O::sqrt(q2);
   const Real t1 = k.sum - x - y - y + k.t1corr * ix;
   const Real t2 = t1 * t1 - (x - k.t2a + k.t2b * ix) * (x - k.t2c + k.t2d * ix) * Real(1.0 / 3.0);
@@ -154,7 +163,10 @@ __device__ __forceinline__ void bw_pairing(const Kin<Real>& k, const Real* __res
       T = Real(1);
     }
     const Real f = O::rsqrt(nq * np);
-    const Real u = qp * O::rcp(sx * nq);
+    // u = q^(2L+1) / (sqrt(x) N_L(q)); in FP32 1/N_L(q) = f^2 N_L(p) saves the reciprocal
+    Real u;
+    if constexpr (sizeof(Real) == 4) u = qp * isx * (f * f * np);
+    else u = qp * O::rcp(sx * nq);
     const Real dre = m2 - x, dim = -delta * u;
     const Real idd = O::rcp(dre * dre + dim * dim);
     const Real num = kappa * f * T * idd;
