@@ -44,22 +44,16 @@ double dot(const std::vector<double>& a, const std::vector<double>& b) {
   return s;
 }
 
+// y = B x for the symmetric BFGS matrix, accumulated row by row as y += x_j B[j, :]: every element is
+// an independent multiply-add, so the loop vectorises (a row-dot form is a chain of dependent adds)
 void matvec(const std::vector<double>& B, const std::vector<double>& x, std::vector<double>& y) {
   const size_t n = x.size();
   y.assign(n, 0.0);
-  for (size_t i = 0; i < n; ++i) {
-    // four partial sums: independent chains the compiler can keep in vector registers
-    const double* Bi = B.data() + i * n;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    size_t j = 0;
-    for (; j + 4 <= n; j += 4) {
-      s0 += Bi[j] * x[j];
-      s1 += Bi[j + 1] * x[j + 1];
-      s2 += Bi[j + 2] * x[j + 2];
-      s3 += Bi[j + 3] * x[j + 3];
-    }
-    for (; j < n; ++j) s0 += Bi[j] * x[j];
-    y[i] = (s0 + s1) + (s2 + s3);
+  double* __restrict__ yy = y.data();
+  for (size_t j = 0; j < n; ++j) {
+    const double xj = x[j];
+    const double* __restrict__ Bj = B.data() + j * n;
+    for (size_t i = 0; i < n; ++i) yy[i] += xj * Bj[i];
   }
 }
 
@@ -226,55 +220,58 @@ int bfgs_fit(const FullEval& fg, int P, const std::vector<int>& polar_pairs, con
   })));
   const double b0 = 0.1 / gmax;  // first step moves the steepest parameter by about 0.1
   for (size_t i = 0; i < n; ++i) B[i * n + i] = b0;
-  std::vector<double> d, Bg;
+  // Bg = B g for the current B.  It is kept up to date through each update, so an iteration takes one
+  // matrix-vector product (B g' with the B the step was taken with; B y = B g' - B g).
+  std::vector<double> d(n), Bg, Bgn, s(n), y(n), By(n), w(n), t(n);
+  matvec(B, g, Bg);
+  auto restart = [&](double b) {  // B = b I
+    std::fill(B.begin(), B.end(), 0.0);
+    for (size_t i = 0; i < n; ++i) B[i * n + i] = b, Bg[i] = b * g[i];
+  };
   int iter = 0, status = MIPWA_E_NOCONV;
   double edm = 0.0;
   bool scaled = false;
   for (; iter < max_iter; ++iter) {
-    matvec(B, g, Bg);
     edm = 0.5 * dot(g, Bg);
     if (edm < tol) {
       status = MIPWA_OK;
       break;
     }
-    d.resize(n);
     for (size_t i = 0; i < n; ++i) d[i] = -Bg[i];
     if (dot(g, d) >= 0) {  // lost positive definiteness: restart from a scaled identity
-      std::fill(B.begin(), B.end(), 0.0);
-      for (size_t i = 0; i < n; ++i) B[i * n + i] = b0, d[i] = -b0 * g[i];
+      restart(b0);
+      for (size_t i = 0; i < n; ++i) d[i] = -Bg[i];
     }
     LineResult lr;
     rc = line_search(obj, x, f, g, d, 1.0, eps_rel * std::fabs(f), lr);
     if (rc) return rc;
     if (!lr.ok) {
       // retry once along steepest descent before giving up
-      std::fill(B.begin(), B.end(), 0.0);
-      for (size_t i = 0; i < n; ++i) B[i * n + i] = b0, d[i] = -b0 * g[i];
+      restart(b0);
+      for (size_t i = 0; i < n; ++i) d[i] = -Bg[i];
       rc = line_search(obj, x, f, g, d, 1.0, eps_rel * std::fabs(f), lr);
       if (rc) return rc;
       if (!lr.ok) break;
     }
-    std::vector<double> s(n), y(n);
     for (size_t i = 0; i < n; ++i) {
       s[i] = lr.x[i] - x[i];
       y[i] = lr.g[i] - g[i];
     }
     const double sy = dot(s, y);
     if (!scaled && sy > 0) {
-      const double sc = sy / dot(y, y);
-      std::fill(B.begin(), B.end(), 0.0);
-      for (size_t i = 0; i < n; ++i) B[i * n + i] = sc;
+      restart(sy / dot(y, y));
       scaled = true;
     }
+    matvec(B, lr.g, Bgn);
     if (sy > 1e-12 * std::sqrt(dot(s, s) * dot(y, y))) {
       const double rho = 1.0 / sy;
-      std::vector<double> By;
-      matvec(B, y, By);
+      for (size_t i = 0; i < n; ++i) By[i] = Bgn[i] - Bg[i];
       const double yBy = dot(y, By);
       // B + (rho^2 y^T B y + rho) s s^T - rho (B y s^T + s y^T B), as B_ij += w_i s_j - s_i t_j with
-      // w = (rho^2 y^T B y + rho) s - rho B y and t = rho B y (two multiply-adds per element)
+      // w = (rho^2 y^T B y + rho) s - rho B y and t = rho B y (two multiply-adds per element).  The
+      // change is symmetric: it is formed on and above the diagonal and mirrored, so B stays exactly
+      // symmetric and B^T x (what matvec forms) is B x.
       const double a = rho * rho * yBy + rho;
-      std::vector<double> w(n), t(n);
       for (size_t i = 0; i < n; ++i) {
         w[i] = a * s[i] - rho * By[i];
         t[i] = rho * By[i];
@@ -282,9 +279,15 @@ int bfgs_fit(const FullEval& fg, int P, const std::vector<int>& polar_pairs, con
       for (size_t i = 0; i < n; ++i) {
         const double wi = w[i], si = s[i];
         double* Bi = B.data() + i * n;
-        for (size_t j = 0; j < n; ++j) Bi[j] += wi * s[j] - si * t[j];
+        for (size_t j = i; j < n; ++j) Bi[j] += wi * s[j] - si * t[j];
       }
+      for (size_t i = 1; i < n; ++i)
+        for (size_t j = 0; j < i; ++j) B[i * n + j] = B[j * n + i];
+      // the updated B times g' = B g' + w (s . g') - s (t . g')
+      const double sg = dot(s, lr.g), tg = dot(t, lr.g);
+      for (size_t i = 0; i < n; ++i) Bgn[i] += w[i] * sg - s[i] * tg;
     }
+    Bg.swap(Bgn);
     x = lr.x;
     f = lr.f;
     g = lr.g;
