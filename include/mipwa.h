@@ -133,7 +133,8 @@ int mipwa_load_norm(mipwa_ctx* ctx, const double* s12, const double* s13, const 
 /* Efficiency table: nx x ny float32 values at the bin centres of [lo, hi]^2 (row-major, index
  * [i12 * ny + i13]), read by bilinear interpolation between centres, constant beyond the outermost
  * centres.  Applied at the next mipwa_load_events / mipwa_load_norm whose eff argument is NULL.
- * Errors: E_INVAL (nx, ny < 2, hi <= lo, a value <= 0). */
+ * Errors: E_INVAL (nx, ny < 2, hi <= lo, a value <= 0), E_HIP (allocation or upload); a failed call
+ * leaves the previous table, or none, in force. */
 int mipwa_set_eff_table(mipwa_ctx* ctx, const float* table, int nx, int ny, double lo, double hi);
 
 /* Parameters held fixed (fixed[p] != 0) in mipwa_fit.  The same mask selects whether mass and width
@@ -268,6 +269,9 @@ int mipwa_server_wait(mipwa_server* s, int64_t job_id, double timeout_s, double*
 /* Cancel a queued or running job (it stops at its next evaluation); other jobs are unaffected. */
 int mipwa_server_cancel(mipwa_server* s, int64_t job_id);
 int mipwa_server_stats(mipwa_server* s, mipwa_serve_stats* stats);
+/* The message of the server's most recent error, from any thread (a failed call, or a failed batched
+ * step: the jobs that step carried end with its status and message).  The string belongs to the
+ * calling thread and stays valid until that thread's next call of this function. */
 const char* mipwa_server_last_error(const mipwa_server* s);
 /* Cancel every job, join the worker threads and free the device memory. */
 void mipwa_server_destroy(mipwa_server* s);

@@ -457,13 +457,17 @@ int mipwa_set_eff_table(mipwa_ctx* ctx, const float* table, int nx, int ny, doub
     if (!(table[i] > 0) || !std::isfinite(table[i]))
       return ctx->fail(MIPWA_E_INVAL, "efficiency table values must be positive");
   (void)hipSetDevice(ctx->device);
+  // the device copy is made first and the table replaced only once it is complete: a failed call
+  // leaves the previous table (or none) in force, never sizes that do not match the device buffer
+  DevBuf d;
+  HIPCHK(d.alloc((size_t)nx * ny * sizeof(float)), "efficiency table allocation");
+  HIPCHK(hipMemcpy(d.p, table, (size_t)nx * ny * sizeof(float), hipMemcpyHostToDevice), "efficiency table upload");
   ctx->eff.tab.assign(table, table + (size_t)nx * ny);
   ctx->eff.nx = nx;
   ctx->eff.ny = ny;
   ctx->eff.lo = lo;
   ctx->eff.hi = hi;
-  HIPCHK(ctx->eff.d.alloc((size_t)nx * ny * sizeof(float)), "efficiency table allocation");
-  HIPCHK(hipMemcpy(ctx->eff.d.p, table, (size_t)nx * ny * sizeof(float), hipMemcpyHostToDevice), "efficiency table upload");
+  ctx->eff.d = std::move(d);
   return MIPWA_OK;
 }
 

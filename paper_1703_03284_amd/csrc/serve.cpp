@@ -99,6 +99,8 @@ struct SJob {
   std::vector<char> staged;  // [Real table | pad to 256 | theta (P doubles)]
   double f = 0;
   std::vector<double> g;
+  int step_rc = 0;        // non-zero: the step that carried this job's evaluation failed
+  std::string step_err;   // and why
   std::mutex m;
   std::condition_variable cv;
   FitOut result;
@@ -181,9 +183,16 @@ struct mipwa_server {
   double* h_res_dev = nullptr;
   std::string err;
 
+  // err is written by the callers' threads and by the scheduler: under its own lock
+  mutable std::mutex err_mu;
   int fail(int code, const std::string& m) {
+    std::lock_guard<std::mutex> g(err_mu);
     err = m;
     return code;
+  }
+  std::string last_error() const {
+    std::lock_guard<std::mutex> g(err_mu);
+    return err;
   }
 };
 
@@ -407,6 +416,7 @@ static void serve_worker(mipwa_server* S, SJob* J) {
       jl.lock();
       J->cv.wait(jl, [&] { return J->done; });
     }
+    if (J->step_rc) return J->step_rc;  // a device failure ends the fit with its status
     f = std::isfinite(J->f) ? J->f : INFINITY;
     std::copy(J->g.begin(), J->g.end(), g);
     return MIPWA_OK;
@@ -417,7 +427,7 @@ static void serve_worker(mipwa_server* S, SJob* J) {
   rc = bfgs_fit(fg, mh.P, pairs, J->fixed, J->theta0.data(), J->tol, J->max_iter, J->hessian,
                 S->fp64 ? 1e-13 : 1e-10, out);
   J->result = out;
-  finish_job(S, J, rc ? rc : out.status, out.err);
+  finish_job(S, J, rc ? rc : out.status, rc && !J->step_err.empty() ? J->step_err : out.err);
 }
 
 namespace {
@@ -610,10 +620,15 @@ void sched_loop(mipwa_server* S) {
     S->steps += 1;
     S->batch_sum += (double)batch.size();
     lk.unlock();
+    const std::string step_err = rc ? S->last_error() : std::string();
     for (SJob* J : batch) {
       {
         std::lock_guard<std::mutex> jl(J->m);
-        if (rc) J->f = NAN;
+        if (rc) {
+          J->f = NAN;
+          J->step_rc = rc;
+          J->step_err = step_err;
+        }
         J->done = true;
       }
       J->cv.notify_one();
@@ -673,7 +688,12 @@ int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double*
                         const double* theta0, const unsigned char* fixed, const mipwa_fit_opts* opts,
                         int64_t* job_id) {
   if (!S) return MIPWA_E_INVAL;
-  if (S->n12.empty()) return S->fail(MIPWA_E_STATE, "set the normalisation sample first");
+  size_t n_norm = 0;
+  {
+    std::lock_guard<std::mutex> g(S->norm_mu);
+    n_norm = S->n12.size();
+  }
+  if (n_norm == 0) return S->fail(MIPWA_E_STATE, "set the normalisation sample first");
   if (!s12 || !s13 || n < 1 || !theta0 || !job_id) return S->fail(MIPWA_E_INVAL, "need events, theta0 and job_id");
   auto J = std::make_unique<SJob>();
   std::string err;
@@ -700,7 +720,7 @@ int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double*
   J->hessian = opts ? opts->hessian != 0 : false;
   const size_t real = S->fp64 ? 8 : 4;
   J->bytes = (size_t)n * ((2 + 2 * R) * real + 16) + (size_t)(n / kTile + 1) * 2 * sizeof(Tile) +
-             S->n12.size() * 2 * (size_t)std::max(R, 1) * real +
+             n_norm * 2 * (size_t)std::max(R, 1) * real +
              (size_t)(2 * kMaxSegBlocks + 32) * record_size(N - 1, R, false) * 8;
   if (J->bytes > S->budget) return S->fail(MIPWA_E_NOMEM, "the job alone exceeds the HBM budget");
   std::lock_guard<std::mutex> lk(S->mu);
@@ -798,7 +818,12 @@ int mipwa_server_stats(mipwa_server* S, mipwa_serve_stats* st) {
   return MIPWA_OK;
 }
 
-const char* mipwa_server_last_error(const mipwa_server* S) { return S ? S->err.c_str() : "server is NULL"; }
+const char* mipwa_server_last_error(const mipwa_server* S) {
+  if (!S) return "server is NULL";
+  thread_local std::string copy;  // the message stays valid while other threads fail
+  copy = S->last_error();
+  return copy.c_str();
+}
 
 void mipwa_server_destroy(mipwa_server* S) {
   if (!S) return;
