@@ -355,10 +355,10 @@ def profile_pass(steps, which="headline"):
     """A few evaluations of one workload plus a 1 GiB device copy of known size (counter calibration)."""
     import torch
     import synth
-    from paper_1703_03284_amd import MIXED
+    from paper_1703_03284_amd import FP64, MIXED
     wl = synth.C4 if which == "shapes" else synth.C3
     table, events, norm = build_inputs(wl, wl.n_events, wl.n_norm)
-    r = time_gpu(wl, MIXED, table, events, norm, steps, 2)
+    r = time_gpu(wl, FP64 if which == "fp64" else MIXED, table, events, norm, steps, 2)
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
@@ -381,7 +381,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=256)
-    ap.add_argument("--profile-pass", nargs="?", const="headline", choices=["headline", "shapes"])
+    ap.add_argument("--profile-pass", nargs="?", const="headline", choices=["headline", "shapes", "fp64"])
     ap.add_argument("--no-shapes", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     args = ap.parse_args()
