@@ -283,6 +283,13 @@ def test_integrals_and_fit_fractions(prec):
         I_o = L.integrals(prob.model, prob.theta, nm)
         I = ctx.integrals(with_eff=with_eff)
         assert np.abs(I - I_o).max() <= tol * np.abs(I_o).max()
+        if with_eff:
+            # the component integrals recombine to the normalisation integral of the likelihood:
+            # I = c^H Ibar c (c_0 = 1), against the oracle's direct sum of w eps |A|^2
+            c = L.coefficient_vector(prob.model, prob.theta)
+            I_tot = float(np.real(np.conj(c) @ I.T @ c))
+            I_dir = L.norm_integral(prob.model, prob.theta, nm)
+            assert abs(I_tot - I_dir) <= tol * I_dir, (I_tot, I_dir)
     ff = ctx.fit_fractions()
     ff_o = L.fit_fractions(prob.model, prob.theta, L.integrals(prob.model, prob.theta, prob.norm))
     assert np.abs(ff - ff_o).max() <= 10 * tol
