@@ -922,7 +922,7 @@ __global__ __launch_bounds__(512) void k_group_sum(const Segment* __restrict__ s
 constexpr int kMaxRecord = 8 * (kMaxKnots - 1) + 1 + 6 * kMaxRes;
 
 constexpr int kMaxConsts = 3 * kMaxKnots - 5;
-constexpr int kFinishThreads = 256;
+constexpr int kFinishThreads = 512;
 
 // One block of kFinishThreads per job.  `jobs` == nullptr: a single job passed by value in `one`
 // (saves the dependent load of its descriptor).
@@ -943,7 +943,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_job_finish(const Job* __rest
   // field f < rs of the data groups, then of the normalisation groups.  Each thread takes up to FPT
   // fields at once and issues the loads of eight groups of all of them before adding, so the sums
   // wait on about one memory round trip; each field's groups are added in group order.
-  constexpr int FPT = 4;
+  constexpr int FPT = 2;
   const int gmax = max(jb.G_d, jb.G_n);
   for (int f0 = threadIdx.x; f0 < nf; f0 += FPT * blockDim.x) {
     // Loads are issued without branches: the field and the group index are clamped to valid records
