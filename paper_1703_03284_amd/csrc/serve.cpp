@@ -174,7 +174,8 @@ struct mipwa_server {
   long long steps = 0;
   double batch_sum = 0;
   // scheduler time (s): idle until a request, in the batching window, staging the step, on the GPU
-  double t_idle = 0, t_window = 0, t_stage = 0, t_gpu = 0;
+  // and handing results back to the jobs' threads, admitting jobs and joining finished ones
+  double t_idle = 0, t_window = 0, t_stage = 0, t_gpu = 0, t_wake = 0, t_admit = 0;
   bool any_submit = false;
   Clock::time_point t_first_submit, t_last_done, t_create = Clock::now();
   std::vector<double> latencies;
@@ -578,9 +579,11 @@ void sched_loop(mipwa_server* S) {
   (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   while (!S->stop) {
+    const auto t_0 = Clock::now();
     admit(S);
     for (auto& kv : S->jobs)
       if (kv.second->state == FINISHED && kv.second->worker.joinable()) kv.second->worker.join();
+    S->t_admit += std::chrono::duration<double>(Clock::now() - t_0).count();
     auto admissible = [&] {
       if (S->queue.empty()) return false;
       SJob* J = S->queue.front();
@@ -621,6 +624,7 @@ void sched_loop(mipwa_server* S) {
     S->batch_sum += (double)batch.size();
     lk.unlock();
     const std::string step_err = rc ? S->last_error() : std::string();
+    const auto t_e = Clock::now();
     for (SJob* J : batch) {
       {
         std::lock_guard<std::mutex> jl(J->m);
@@ -634,6 +638,7 @@ void sched_loop(mipwa_server* S) {
       J->cv.notify_one();
     }
     lk.lock();
+    S->t_wake += std::chrono::duration<double>(Clock::now() - t_e).count();
     if (S->steps % 256 == 1) trace(S, "step %lld: batch %zu of %d active", S->steps, batch.size(), S->n_active);
   }
 }
@@ -839,8 +844,9 @@ void mipwa_server_destroy(mipwa_server* S) {
   if (S->sched.joinable()) S->sched.join();
   for (auto& kv : S->jobs)
     if (kv.second->worker.joinable()) kv.second->worker.join();
-  trace(S, "scheduler: %lld steps; idle %.3f s, batching window %.3f s, staging %.3f s, launch to results %.3f s",
-        S->steps, S->t_idle, S->t_window, S->t_stage, S->t_gpu);
+  trace(S, "scheduler: %lld steps; idle %.3f s, batching window %.3f s, staging %.3f s, launch to results %.3f s, "
+        "results to the jobs %.3f s, admission and joins %.3f s",
+        S->steps, S->t_idle, S->t_window, S->t_stage, S->t_gpu, S->t_wake, S->t_admit);
   (void)hipSetDevice(S->device);
   (void)hipStreamSynchronize(S->stream);
   S->jobs.clear();
