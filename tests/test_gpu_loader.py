@@ -132,3 +132,23 @@ def test_region_tolerance_at_the_boundary():
     a3[-1] = K.smin(m) - 3.0 * tol
     _raises(lambda: ctx.load_events(a3, b), -1, "point 8 ")
     ctx.close()
+
+
+def test_rejected_efficiency_table_leaves_the_previous_one():
+    """A table that fails validation changes nothing: points loaded afterwards without per-point
+    efficiencies still take the previous table, and the evaluation agrees with the oracle."""
+    prob = make_problem(synth.C3, 3000, 8000, seed=41)
+    ctx = prob.context(_fp64(), table_mode=True)
+    v1, g1 = ctx.eval()
+    bad = np.array(prob.table, dtype=np.float32)
+    bad[3, 5] = 0.0
+    d = synth.C3.decay
+    _raises(lambda: ctx.set_eff_table(bad, d.smin, d.smax), -1, "positive")
+    _raises(lambda: ctx.set_eff_table(bad[:1], d.smin, d.smax), -1, "nx, ny >= 2")
+    ctx.load_events(*prob.events)
+    ctx.load_norm(*prob.norm)
+    v2, g2 = ctx.eval(prob.theta)
+    ctx.close()
+    assert v2 == v1 and np.array_equal(g2, g1)
+    v_o, _ = prob.oracle()
+    assert rel(v2, v_o) <= 1e-10, (v2, v_o)
