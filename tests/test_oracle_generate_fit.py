@@ -86,3 +86,72 @@ def test_fit_closure_small_toy():
     pulls = d[free] / res["sigma"][free]
     assert np.all(np.abs(pulls) < 5), pulls
     assert abs(pulls.mean()) < 1.0
+
+
+def test_fmax_doubling_restart():
+    """With a probe of only three candidates, 1.5 x the probe maximum is below the largest density
+    the generator meets, so f_max is doubled and generation restarts from the first candidate.  The
+    sample returned is exactly the accept-reject sample at the final f_max (nothing accepted under a
+    smaller f_max survives), the final f_max is the probe value times a power of two, and half of it
+    would have been exceeded (the last doubling was needed)."""
+    w = synth.C1
+    m = oracle_model(w)
+    th = w.truth()
+    probe = G.density_max(m, th, 77 + 1000, 3)
+    s12, s13, fmax = G.toy(m, th, 300, seed=77, n_probe=3)
+    k = np.log2(fmax / (1.5 * probe))
+    assert k >= 1 and k == round(k)
+    r12, r13, exceeded = G.accept_reject(m, th, 300, 77, fmax)
+    assert not exceeded
+    assert np.array_equal(s12, r12) and np.array_equal(s13, r13)
+    _, _, exceeded_half = G.accept_reject(m, th, 300, 77, fmax / 2)
+    assert exceeded_half
+    # every density met on the way to the 300th acceptance is below the final f_max
+    c12, c13, _ = G.candidates(m, 77, 0, 1 << 20)
+    ok = K.inside(m, c12, c13)
+    assert G.density(m, th, c12[ok], c13[ok]).max() <= fmax
+
+
+@pytest.mark.slow
+def test_covariance_matches_inverse_expected_information():
+    """The fit's covariance V = 2 H^-1 (H the Hessian of -2 ln L) equals, up to the statistical
+    spread of the observed Hessian, the inverse of the expected information n Cov_P(grad ln|A|^2)
+    (Sec. 4 judges fitted values by their errors).  The information is computed by brute force, per
+    point, from central differences of ln|A|^2 over a large uniform sample weighted by the density:
+    no part of it uses the fit's Hessian.  A covariance of H^-1 (a factor 2 off in variance) or one
+    taken from the Hessian of -ln L without the factor would fail by a factor of 2."""
+    from oracle import Model, Res
+    d = synth.D_PIPIPI
+    N = 6
+    knots = tuple(synth.uniform_knots(d, N))
+    m = Model(d.M, d.m1, d.m2, d.m3, d.rD, knots, (Res(1, 0.775, 0.149, 1.5),))
+    truth = synth.truth_theta(N, (synth.RHO770,), 4242)
+    fixed = synth.fixed_mask(N, 1)
+    s12, s13, _ = G.toy(m, truth, 20000, seed=4243, n_probe=200_000)
+    n12, n13 = synth.uniform_phase_space(d, 60000, 4244)
+    w = np.full(len(n12), K.area(m) / len(n12))
+    start = synth.perturb_theta(truth, N, 1, 4245)
+    res = F.fit(m, start, (s12, s13), (n12, n13, w), fixed, gtol=1e-6)
+    free = np.flatnonzero(fixed == 0)
+    th = res["theta_raw"]
+    # expected information per event: Cov_P of grad ln|A|^2 over the uniform sample, P = w|A|^2 / I
+    u12, u13 = synth.uniform_phase_space(d, 400000, 4246)
+    a = L.amplitude(m, th, u12, u13)
+    p = a.real ** 2 + a.imag ** 2
+    p = p / p.sum()
+    grads = np.empty((len(free), len(u12)))
+    for i, k in enumerate(free):
+        h = 1e-5 * max(1.0, abs(th[k]))
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        ap, am = L.amplitude(m, tp, u12, u13), L.amplitude(m, tm, u12, u13)
+        grads[i] = (np.log(ap.real ** 2 + ap.imag ** 2) - np.log(am.real ** 2 + am.imag ** 2)) / (2 * h)
+    mean = grads @ p
+    c = grads - mean[:, None]
+    info = len(s12) * (c * p) @ c.T
+    v_expected = np.linalg.inv(info)
+    v_fit = res["cov"][np.ix_(free, free)]
+    ratio = np.diag(v_fit) / np.diag(v_expected)
+    assert np.all((ratio > 0.8) & (ratio < 1.25)), ratio
+    assert abs(np.median(ratio) - 1.0) < 0.1, ratio

@@ -135,3 +135,84 @@ def test_symmetrisation_is_exact(pipipi, rng):
         a = R.symmetrised(pipipi, res, s12, s13)
         b = R.symmetrised(pipipi, res, s13, s12)
         assert np.array_equal(a, b)
+
+
+def _case_model(base, case):
+    from oracle import Model, Res
+    return Model(base.M, base.m1, base.m2, base.m3, case["rD"], base.knots,
+                 (Res(case["spin"], case["mass"], case["width"], case["radius"]),))
+
+
+def _offpole_cases():
+    return json.load(open(os.path.join(GOLDEN, "bw_offpole.json")))["cases"]
+
+
+def test_offpole_hand_values(pipipi):
+    """Off the pole each factor of the dynamical part differs from 1, so the hand-worked values pin
+    which momentum enters which barrier factor with which radius (Sec. 2 Breit-Wigner)."""
+    for c in _offpole_cases():
+        m = _case_model(pipipi, c)
+        res = m.res[0]
+        x = np.array([c["x"]])
+        assert R.daughter_momentum(x, m.m1, m.m2)[0] == pytest.approx(c["q"], rel=1e-13)
+        assert R.bachelor_momentum(x, m.M, m.m3)[0] == pytest.approx(c["p"], rel=1e-13)
+        assert R.blatt_weisskopf(res.spin, x * 0 + c["q"], c["q_r"], res.radius)[0] == pytest.approx(c["B_q"], rel=1e-13)
+        assert R.blatt_weisskopf(res.spin, x * 0 + c["p"], c["p_r"], m.rD)[0] == pytest.approx(c["B_p"], rel=1e-13)
+        assert R.running_width(m, res, x)[0] == pytest.approx(c["running_width"], rel=1e-12)
+        d = R.dynamical(m, res, x)[0]
+        assert d.real == pytest.approx(c["re"], rel=1e-12)
+        assert d.imag == pytest.approx(c["im"], rel=1e-12)
+
+
+def test_textbook_rbw_reduction(pipipi):
+    """With L = 0 and both barrier radii zero the dynamical part is the textbook relativistic
+    Breit-Wigner in the mass m = sqrt(x): 1 / (m_r^2 - m^2 - i m_r Gamma_r (q/q_r)(m_r/m)), with the
+    pion momentum q = sqrt(m^2/4 - m_pi^2); checked at points away from the pole on both sides."""
+    from oracle import Model, Res
+    mr, gr = 0.990, 0.060
+    m = Model(pipipi.M, pipipi.m1, pipipi.m2, pipipi.m3, 0.0, pipipi.knots, (Res(0, mr, gr, 0.0),))
+    mass = np.linspace(0.3, 1.7, 57)
+    qq = np.sqrt(mass ** 2 / 4 - pipipi.m1 ** 2)
+    q0 = np.sqrt(mr ** 2 / 4 - pipipi.m1 ** 2)
+    textbook = 1.0 / (mr ** 2 - mass ** 2 - 1j * mr * gr * (qq / q0) * (mr / mass))
+    got = R.dynamical(m, m.res[0], mass ** 2)
+    np.testing.assert_allclose(got.real, textbook.real, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(got.imag, textbook.imag, rtol=1e-12, atol=1e-14)
+    c = _offpole_cases()[2]
+    d = R.dynamical(m, m.res[0], np.array([c["x"]]))[0]
+    assert (d.real, d.imag) == (pytest.approx(c["re"], rel=1e-12), pytest.approx(c["im"], rel=1e-12))
+
+
+def _planted(kind):
+    """The dynamical part with one plausible mistake planted (test of the pins above)."""
+    def dyn(model, res, x):
+        q = R.daughter_momentum(x, model.m1, model.m2)
+        q_r = R.daughter_momentum(res.mass ** 2, model.m1, model.m2)
+        p = R.bachelor_momentum(x, model.M, model.m3)
+        p_r = R.bachelor_momentum(res.mass ** 2, model.M, model.m3)
+        rr, rd = (model.rD, res.radius) if kind == "radii swapped" else (res.radius, model.rD)
+        bq = R.blatt_weisskopf(res.spin, q, q_r, rr)
+        if kind == "no D factor":
+            bp = 1.0
+        elif kind == "q for p":
+            bp = R.blatt_weisskopf(res.spin, q, q_r, rd)
+        else:
+            bp = R.blatt_weisskopf(res.spin, p, p_r, rd)
+        gam = res.width * (q / q_r) ** (2 * res.spin + 1) * (res.mass / np.sqrt(x)) * bq * bq
+        return bq * bp / (res.mass ** 2 - x - 1j * res.mass * gam)
+    return dyn
+
+
+@pytest.mark.parametrize("kind", ["radii swapped", "no D factor", "q for p"])
+def test_offpole_pins_reject_planted_mistakes(pipipi, kind):
+    """Each planted mistake moves an off-pole hand value by more than 1%; at the pole all of them
+    agree with the correct form (which is why the pole pin alone could not see them)."""
+    dyn = _planted(kind)
+    worst = 0.0
+    for c in _offpole_cases()[:2]:
+        m = _case_model(pipipi, c)
+        d = dyn(m, m.res[0], np.array([c["x"]]))[0]
+        worst = max(worst, abs(d - complex(c["re"], c["im"])) / abs(complex(c["re"], c["im"])))
+        pole = dyn(m, m.res[0], np.array([c["mass"] ** 2]))[0]
+        assert abs(pole - 1j / (c["mass"] * c["width"])) < 1e-9 * abs(pole)
+    assert worst > 1e-2
