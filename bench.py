@@ -218,8 +218,9 @@ def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
         wall = time.perf_counter() - start
         st = srv.stats()
         srv.close()
-        ok = sum(1 for r in res if r["status"] in (0, -6))
-        return wall, st, ok, res
+        n_ok = sum(1 for r in res if r["status"] == 0)
+        n_noconv = sum(1 for r in res if r["status"] == -6)
+        return wall, st, (n_ok, n_noconv), res
 
     wall0, st0, ok0, _ = run(None)
     capacity = st0["fits_per_s"]
@@ -232,16 +233,17 @@ def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
             "capacity_fits_per_s": capacity, "arrival_rate_per_s": rate,
             "fits_per_s": st1["fits_per_s"], "p50_s": st1["p50_s"], "p99_s": st1["p99_s"],
             "mean_batch": st1["mean_batch"], "steps": st1["steps"], "peak_bytes": st1["peak_bytes"],
-            "converged": ok1, "mean_evals_per_fit": float(np.mean([r.get("n_eval", 0) for r in res1])),
+            "converged": ok1[0], "not_converged": ok1[1], "tol_edm": 1e-4,
+            "mean_evals_per_fit": float(np.mean([r.get("n_eval", 0) for r in res1])),
             "precision": "mixed" if precision == 1 else "fp64"}
 
 
 def paper_fit(precision_name="fp64"):
     """The paper's fit (Sec. 4) on synthetic input: D+ -> K-K+K+, 40 knots, phi(1020), 100k toy events
     generated on the device at the truth, fitted (BFGS from a perturbed start, Hessian at the end)
-    with the normalisation integral on the evenly spaced grid at each spacing of Fig. 3.  Reports the
+    with the normalisation integral on the evenly spaced grid at each spacing of Fig. 2.  Reports the
     fit wall time (the paper's Table 1 times this fit on 2014-era GPUs) and the pulls of the fitted
-    knot values against the input (the quantity Fig. 3 plots)."""
+    knot values against the input (the quantity Fig. 2 plots)."""
     import synth
     from paper_1703_03284_amd import FP64, MIXED, context_for
     wl = synth.KKK

@@ -208,6 +208,15 @@ int mipwa_generate(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t se
 int mipwa_density_max(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t seed, int64_t n_probe,
                       double* fmax_out);
 
+/* The whole toy procedure (Sec. 4: toy samples generated from the Dalitz-plot PDF; the bound rule is
+ * this library's reading, the paper states none): fmax = 1.5 x mipwa_density_max over n_probe
+ * inside-candidates of key seed + 1000, then mipwa_generate with key `seed`; while any examined
+ * candidate exceeds fmax, fmax is doubled and the sample drawn again from the first candidate.  Writes
+ * n points to the host arrays s12_out, s13_out and the final bound to *fmax_out (nullable).  Errors:
+ * as mipwa_generate, and E_INVAL for n_probe < 1 or a zero density over the probe. */
+int mipwa_toy(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t seed, int64_t n_probe, int64_t n,
+              double* s12_out, double* s13_out, double* fmax_out);
+
 /* Device time of the most recent evaluation's kernels in milliseconds (HIP events around the resonance
  * cache build, the streaming likelihood kernel and the reduction); *stream_ms is the streaming kernel
  * alone.  Nullable outputs. */

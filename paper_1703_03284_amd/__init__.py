@@ -236,14 +236,14 @@ class Context:
         return out.value
 
     def toy(self, theta, n, seed, n_probe=1_000_000):
-        """Accept-reject toy with fmax = 1.5 x the largest density over n_probe inside-candidates of
-        key seed + 1000, doubled and restarted if any candidate exceeds it."""
-        fmax = 1.5 * self.density_max(theta, seed + 1000, n_probe)
-        while True:
-            s12, s13, exceeded, _ = self.generate(theta, n, seed, fmax)
-            if not exceeded:
-                return s12, s13, fmax
-            fmax *= 2.0
+        """Accept-reject toy sample of n points (mipwa_toy): fmax = 1.5 x the largest density over
+        n_probe inside-candidates of key seed + 1000, doubled and redrawn while exceeded."""
+        t = _f64(theta)
+        s12, s13 = np.empty(n), np.empty(n)
+        fmax = C.c_double()
+        self._check(self._lib.mipwa_toy(self._h, L.dptr(t), len(t), int(seed), int(n_probe), int(n),
+                                        L.dptr(s12), L.dptr(s13), C.byref(fmax)), "toy")
+        return s12, s13, fmax.value
 
 
 def context_for(decay, knots, resonances, precision=FP64, device=0) -> Context:

@@ -62,6 +62,7 @@ SIGNATURES = {
     "mipwa_generate": (C.c_int, [_P, _D, C.c_int, C.c_ulonglong, C.c_double, _I64, _D, _D,
                                  C.POINTER(C.c_int), C.POINTER(_I64)]),
     "mipwa_density_max": (C.c_int, [_P, _D, C.c_int, C.c_ulonglong, _I64, _D]),
+    "mipwa_toy": (C.c_int, [_P, _D, C.c_int, C.c_ulonglong, _I64, _I64, _D, _D, _D]),
     "mipwa_last_timing": (C.c_int, [_P, _D, _D]),
     "mipwa_set_launch": (C.c_int, [_P, C.c_int, C.c_int]),
     "mipwa_set_timing": (C.c_int, [_P, C.c_int]),

@@ -52,6 +52,12 @@ struct mipwa_ctx {
   // Timing events: two sets [before the sweep, sweep start, sweep end, after the finish] used in
   // turn, so that an evaluation reads the previous one's times after its own launches are queued.
   hipEvent_t ev_staged = nullptr;
+  // Completion of the last enqueued evaluation and the stream it went to.  The context's scratch
+  // (records, group records, tables, resonance cache, moments) is shared by every stream an
+  // evaluation may be queued on, so the next enqueue on another stream waits for this event, and
+  // host-side replacement of those buffers first waits for it.
+  hipEvent_t ev_done = nullptr;
+  hipStream_t last_st = nullptr;
   hipEvent_t ev_t[2][4] = {};
   int ev_cur = 0;                 // set the next timed evaluation records into
   int ev_last = 0;                // set of the last timed evaluation
@@ -67,6 +73,7 @@ struct mipwa_ctx {
 
   ~mipwa_ctx() {
     if (ev_staged) (void)hipEventDestroy(ev_staged);
+    if (ev_done) (void)hipEventDestroy(ev_done);
     for (auto& set : ev_t)
       for (hipEvent_t e : set)
         if (e) (void)hipEventDestroy(e);
@@ -91,4 +98,8 @@ struct mipwa_ctx {
   int fold_timing(int set);
   int fold_all_timing();
   int run_sync_eval();
+  // order work about to go on stream st after the last evaluation queued on any other stream
+  int order_after_last(hipStream_t st);
+  // block the host until every evaluation queued so far, on any stream, has completed
+  int drain();
 };

@@ -79,13 +79,20 @@ struct LineResult {
   std::vector<double> x, g;
 };
 
-// strong-Wolfe line search along d from (x0, f0, g0); eps_f is the tolerated noise in f
+// Line search along d from (x0, f0, g0) for a step meeting the strong Wolfe conditions (Nocedal &
+// Wright, ch. 3: expansion until a bracket is found, then zoom by safeguarded cubic interpolation),
+// with the sufficient-decrease test relaxed by eps_f, the noise of f.  The bracket is kept by the
+// sign of the directional derivative, as in Hager & Zhang's line search (SIAM J. Optim. 16, 2005):
+// lo always has phi' < 0 and f <= f0 + eps_f, hi has phi' >= 0 or f above f0 + eps_f.  Comparisons
+// of f values that differ by less than the noise decide nothing, so near the minimum, where the
+// decrease per step falls below the rounding noise of a mixed-precision f, the search is steered by
+// the gradient, which stays accurate there.
 int line_search(Objective& obj, const std::vector<double>& x0, double f0, const std::vector<double>& g0,
                 const std::vector<double>& d, double alpha0, double eps_f, LineResult& out) {
   const double c1 = 1e-4, c2 = 0.9;
   const double dphi0 = dot(g0, d);
   const size_t n = x0.size();
-  std::vector<double> x(n), g;
+  std::vector<double> x(n);
   auto eval = [&](double a, double& f, double& dphi, std::vector<double>& gx) -> int {
     for (size_t i = 0; i < n; ++i) x[i] = x0[i] + a * d[i];
     int rc = obj(x, f, gx);
@@ -100,6 +107,10 @@ int line_search(Objective& obj, const std::vector<double>& x0, double f0, const 
     out.x = x;
     out.g = gx;
   };
+  auto wolfe = [&](double a, double f, double dp) {
+    return f <= f0 + c1 * a * dphi0 + eps_f && std::fabs(dp) <= -c2 * dphi0;
+  };
+  // lo: phi' < 0 and f <= f0 + eps_f (a = 0 qualifies); hi: the other end of the bracket
   auto zoom = [&](double lo, double flo, double dlo, double hi, double fhi, double dhi) -> int {
     for (int it = 0; it < 30; ++it) {
       const double a = cubic_step(lo, flo, dlo, hi, fhi, dhi);
@@ -107,33 +118,29 @@ int line_search(Objective& obj, const std::vector<double>& x0, double f0, const 
       std::vector<double> gx;
       int rc = eval(a, f, dp, gx);
       if (rc) return rc;
-      if (!std::isfinite(f) || f > f0 + c1 * a * dphi0 + eps_f || f >= flo) {
+      if (std::isfinite(f) && wolfe(a, f, dp)) {
+        accept(a, f, gx);
+        return MIPWA_OK;
+      }
+      if (!std::isfinite(f) || dp >= 0 || f > f0 + eps_f) {
         hi = a;
         fhi = f;
         dhi = dp;
       } else {
-        if (std::fabs(dp) <= -c2 * dphi0) {
-          accept(a, f, gx);
-          return MIPWA_OK;
-        }
-        if (dp * (hi - lo) >= 0) {
-          hi = lo;
-          fhi = flo;
-          dhi = dlo;
-        }
         lo = a;
         flo = f;
         dlo = dp;
       }
       if (std::fabs(hi - lo) < 1e-16 * std::max(1.0, std::fabs(lo))) break;
     }
-    // no point met both conditions: take the best sufficient-decrease point if it improved f
-    if (lo > 0 && flo < f0) {
+    // no point met both conditions: move to lo if it lies beyond the start (its f is within the
+    // noise of f0 or below, and the function still descends there)
+    if (lo > 0) {
       double f, dp;
       std::vector<double> gx;
       int rc = eval(lo, f, dp, gx);
       if (rc) return rc;
-      accept(lo, f, gx);
+      if (std::isfinite(f) && f <= f0 + eps_f) accept(lo, f, gx);
     }
     return MIPWA_OK;
   };
@@ -144,13 +151,11 @@ int line_search(Objective& obj, const std::vector<double>& x0, double f0, const 
     std::vector<double> gx;
     int rc = eval(a, f, dp, gx);
     if (rc) return rc;
-    if (!std::isfinite(f) || f > f0 + c1 * a * dphi0 + eps_f || (it > 0 && f >= f_prev))
-      return zoom(a_prev, f_prev, d_prev, a, f, dp);
-    if (std::fabs(dp) <= -c2 * dphi0) {
+    if (std::isfinite(f) && wolfe(a, f, dp)) {
       accept(a, f, gx);
       return MIPWA_OK;
     }
-    if (dp >= 0) return zoom(a, f, dp, a_prev, f_prev, d_prev);
+    if (!std::isfinite(f) || dp >= 0 || f > f0 + eps_f) return zoom(a_prev, f_prev, d_prev, a, f, dp);
     a_prev = a;
     f_prev = f;
     d_prev = dp;
@@ -377,8 +382,7 @@ extern "C" int mipwa_fit(mipwa_ctx* ctx, const mipwa_fit_opts* opts, double* the
     }
     return rc;
   };
-  // FP32 streams leave ~1e-11 relative noise in f; allow it in the sufficient-decrease test
-  const double eps_rel = ctx->fp64 ? 1e-13 : 1e-10;
+  const double eps_rel = ctx->fp64 ? kNoiseRelFp64 : kNoiseRelMixed;
   FitOut out;
   // (magnitude, phase) pairs of the external layout: the polar knots, c_NR of the isobar form, the c_r
   std::vector<int> pairs;

@@ -150,4 +150,24 @@ int mipwa_density_max(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t
   return MIPWA_OK;
 }
 
+int mipwa_toy(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t seed, int64_t n_probe, int64_t n,
+              double* s12_out, double* s13_out, double* fmax_out) {
+  if (!ctx) return MIPWA_E_INVAL;
+  if (n_probe < 1) return ctx->fail(MIPWA_E_INVAL, "need n_probe >= 1");
+  double fmax = 0.0;
+  int rc = mipwa_density_max(ctx, theta, n_theta, seed + 1000, n_probe, &fmax);
+  if (rc) return rc;
+  if (!(fmax > 0.0) || !std::isfinite(fmax)) return ctx->fail(MIPWA_E_INVAL, "the density is zero or not finite over the probe");
+  fmax *= 1.5;
+  for (;;) {
+    int exceeded = 0;
+    rc = mipwa_generate(ctx, theta, n_theta, seed, fmax, n, s12_out, s13_out, &exceeded, nullptr);
+    if (rc) return rc;
+    if (!exceeded) break;
+    fmax *= 2.0;
+  }
+  if (fmax_out) *fmax_out = fmax;
+  return MIPWA_OK;
+}
+
 }  // extern "C"

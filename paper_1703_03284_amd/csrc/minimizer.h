@@ -19,6 +19,11 @@ struct FitOut {
   std::string err;
 };
 
+// Noise of f, relative to |f|, that the line search tolerates.  In mixed precision the per-point FP32
+// rounding of ln|A|^2 and |A|^2 sums to ~1e-5 absolute at 10^4 events (f ~ 2.5e4) and grows with the
+// event count; 1e-8 |f| covers it at every size, and the search then decides by the gradient's sign.
+constexpr double kNoiseRelFp64 = 1e-13, kNoiseRelMixed = 1e-8;
+
 // polar_pairs: indices i of (magnitude, phase) pairs (theta[i], theta[i+1]) folded to magnitude >= 0,
 // phase in (-pi, pi] at the end
 int bfgs_fit(const FullEval& fg, int P, const std::vector<int>& polar_pairs, const std::vector<unsigned char>& fixed,

@@ -65,8 +65,8 @@ static std::atomic<unsigned long long> g_eval_seq{0};
 
 int mipwa_ctx::rebuild_launch() {
   mipwa_ctx* ctx = this;
-  // the buffers below are replaced: nothing queued may still use them
-  HIPCHK(hipStreamSynchronize(stream), "stream sync");
+  // the buffers below are replaced: nothing queued, on any stream, may still use them
+  if (int rc = drain()) return rc;
   const int waves = waves_cfg ? waves_cfg : 4;
   waves_eff = waves;
   const bool qf = use_qform();
@@ -204,6 +204,9 @@ bool mipwa_ctx::shapes_changed() const {
 int mipwa_ctx::ensure_cache(hipStream_t st) {
   mipwa_ctx* ctx = this;
   if (!shapes_changed()) return MIPWA_OK;
+  // the resonance constants are replaced from the host and the cache rewritten: every evaluation
+  // still reading them, on any stream, must have finished
+  if (int rc = drain()) return rc;
   HIPCHK(hipStreamSynchronize(st), "stream sync");
   if (int rc = mh.upload_res64(theta.data(), d_res64)) return fail(rc, "resonance constants upload failed");
   PointSet* ps[2] = {&ev, &nm};
@@ -214,6 +217,19 @@ int mipwa_ctx::ensure_cache(hipStream_t st) {
   cache_shape.assign(theta.begin() + 2 * mh.N + 2 * mh.R, theta.end());
   cache_valid = ev.loaded && nm.loaded;
   mom_valid = false;  // the moments hold the normalisation points' resonance amplitudes
+  return MIPWA_OK;
+}
+
+int mipwa_ctx::order_after_last(hipStream_t st) {
+  mipwa_ctx* ctx = this;
+  if (last_st != nullptr && last_st != st) HIPCHK(hipStreamWaitEvent(st, ev_done, 0), "stream wait");
+  return MIPWA_OK;
+}
+
+int mipwa_ctx::drain() {
+  mipwa_ctx* ctx = this;
+  if (last_st != nullptr) HIPCHK(hipEventSynchronize(ev_done), "event sync");
+  HIPCHK(hipStreamSynchronize(stream), "stream sync");
   return MIPWA_OK;
 }
 
@@ -233,6 +249,8 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigne
   HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), d_tasks.as<int2>(), n_tasks, 1,
                        use_arg ? &h_args : nullptr, st, s, out, &h_jobs[to_host ? 0 : 1]),
          "reduction kernels");
+  HIPCHK(hipEventRecord(ev_done, st), "event");
+  last_st = st;
   if (timed) {
     HIPCHK(hipEventRecord(ev_t[cs][3], st), "event");
     ev_last = cs;
@@ -251,7 +269,9 @@ int mipwa_ctx::prepare_eval(hipStream_t st) {
     int rc = rebuild_launch();
     if (rc) return rc;
   }
-  int rc = stage_params();
+  int rc = order_after_last(st);
+  if (rc) return rc;
+  rc = stage_params();
   if (rc) return rc;
   if (!otf && shapes_changed()) {
     rc = ensure_cache(st);
@@ -361,7 +381,8 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
     delete ctx;
     return MIPWA_E_HIP;
   }
-  bool events_ok = hipEventCreate(&ctx->ev_staged) == hipSuccess;
+  bool events_ok = hipEventCreate(&ctx->ev_staged) == hipSuccess &&
+                   hipEventCreateWithFlags(&ctx->ev_done, hipEventDisableTiming) == hipSuccess;
   for (auto& set : ctx->ev_t)
     for (hipEvent_t& e : set) events_ok = events_ok && hipEventCreate(&e) == hipSuccess;
   if (!events_ok) {
@@ -410,7 +431,7 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
 void mipwa_destroy(mipwa_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  (void)ctx->drain();
   delete ctx;
 }
 
@@ -476,7 +497,7 @@ int mipwa_set_eff_table(mipwa_ctx* ctx, const float* table, int nx, int ny, doub
 int mipwa_load_events(mipwa_ctx* ctx, const double* s12, const double* s13, const double* eff, int64_t n) {
   if (!ctx) return MIPWA_E_INVAL;
   (void)hipSetDevice(ctx->device);
-  HIPCHK(hipStreamSynchronize(ctx->stream), "stream sync");
+  if (int rc = ctx->drain()) return rc;
   int rc = load_points(ctx->mh, ctx->fp64, 0, s12, s13, nullptr, eff, n, ctx->eff, ctx->stream, ctx->ev, ctx->err);
   ctx->cache_valid = false;
   ctx->launch_dirty = true;
@@ -487,7 +508,7 @@ int mipwa_load_norm(mipwa_ctx* ctx, const double* s12, const double* s13, const 
                     int64_t n) {
   if (!ctx) return MIPWA_E_INVAL;
   (void)hipSetDevice(ctx->device);
-  HIPCHK(hipStreamSynchronize(ctx->stream), "stream sync");
+  if (int rc = ctx->drain()) return rc;
   int rc = load_points(ctx->mh, ctx->fp64, 1, s12, s13, w, eff, n, ctx->eff, ctx->stream, ctx->nm, ctx->err);
   ctx->cache_valid = false;
   ctx->launch_dirty = true;
@@ -589,6 +610,8 @@ int mipwa_integrals(mipwa_ctx* ctx, int with_eff, double* Ijk) {
   if (!ctx->have_theta) return ctx->fail(MIPWA_E_STATE, "set parameters first");
   (void)hipSetDevice(ctx->device);
   hipStream_t st = ctx->stream;
+  // the normalisation cache is rewritten below: evaluations still reading it must finish first
+  if (int rc = ctx->drain()) return rc;
   if (ctx->launch_dirty && ctx->ev.loaded) {
     int rc = ctx->rebuild_launch();
     if (rc) return rc;

@@ -426,7 +426,7 @@ static void serve_worker(mipwa_server* S, SJob* J) {
   std::vector<int> pairs;
   for (int k = 0; k < mh.N + mh.R; ++k) pairs.push_back(2 * k);
   rc = bfgs_fit(fg, mh.P, pairs, J->fixed, J->theta0.data(), J->tol, J->max_iter, J->hessian,
-                S->fp64 ? 1e-13 : 1e-10, out);
+                S->fp64 ? kNoiseRelFp64 : kNoiseRelMixed, out);
   J->result = out;
   finish_job(S, J, rc ? rc : out.status, rc && !J->step_err.empty() ? J->step_err : out.err);
 }

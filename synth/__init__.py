@@ -101,7 +101,7 @@ def inside_region(decay: Decay, s12, s13):
 def grid_points(decay: Decay, spacing: float):
     """Evenly spaced normalisation points (Sec. 4): the centres of the square cells of side `spacing`
     (GeV^2) of a grid anchored at (s_min, s_min) that lie inside the Dalitz region, each weighted by
-    the cell area spacing^2.  Fig. 3 uses spacings of 0.01, 0.004 and 0.001 GeV^2.
+    the cell area spacing^2.  Fig. 2 uses spacings of 0.01, 0.004 and 0.001 GeV^2.
 
     Returns (s12, s13, w), row by row in s12 and, within a row, increasing s13."""
     lo, hi = decay.smin, decay.smax

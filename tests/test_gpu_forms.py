@@ -20,9 +20,8 @@ def _prec(name):
     return {"fp64": FP64, "mixed": MIXED}[name]
 
 
-def _nll_ok(v, v_o, prec, scale):
-    tn = TOL[prec][0]
-    return rel(v, v_o) <= tn if prec == "fp64" else abs(v - v_o) <= tn * scale
+def _nll_ok(v, v_o, prec, scale=None):
+    return rel(v, v_o) <= TOL[prec][0]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

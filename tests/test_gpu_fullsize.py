@@ -132,3 +132,36 @@ def test_torch_autograd_and_device_output():
     host = dev.cpu().numpy()
     assert host[0] == v
     np.testing.assert_array_equal(host[1:], g)
+
+
+def test_async_evaluation_on_another_stream_is_ordered():
+    """An evaluation queued on torch's stream, followed at once (no host synchronisation) by
+    synchronous evaluations on the context's own stream at other parameters -- one of them with new
+    resonance shapes, which rebuilds the amplitude cache -- gives every result bitwise equal to the
+    same evaluations run one after another."""
+    import torch
+    from paper_1703_03284_amd.torch_nll import nll_on_device
+    prob = make_problem(synth.C2, 400_000, 1_000_000, seed=13)
+    ctx = prob.context(_prec("mixed"))
+    th1 = prob.theta.copy()
+    th2 = th1.copy()
+    th2[0] *= 1.01
+    th3 = th1.copy()
+    th3[-3] += 0.004  # a mass: the cache is rebuilt
+    seq = [ctx.eval(t) for t in (th1, th2, th3, th1)]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        dev = [nll_on_device(torch.tensor(th1), ctx) for _ in range(3)]
+    r2 = ctx.eval(th2)
+    with torch.cuda.stream(side):
+        dev.append(nll_on_device(torch.tensor(th1), ctx))
+    r3 = ctx.eval(th3)
+    r1 = ctx.eval(th1)
+    torch.cuda.synchronize()
+    for d in dev:
+        h = d.cpu().numpy()
+        assert h[0] == seq[0][0] and np.array_equal(h[1:], seq[0][1])
+    for (v, g), (vs, gs) in ((r2, seq[1]), (r3, seq[2]), (r1, seq[3])):
+        assert v == vs and np.array_equal(g, gs)
+    ctx.close()

@@ -1,4 +1,4 @@
-"""The paper's own normaliser (Sec. 4): the evenly spaced grid of Fig. 3, evaluated by the library
+"""The paper's own normaliser (Sec. 4): the evenly spaced grid of Fig. 2, evaluated by the library
 against the oracle on the same grid points."""
 import numpy as np
 import pytest
@@ -24,8 +24,12 @@ def test_grid_normalisation_matches_oracle(wl, spacing, n_ev, prec):
     v, g = ctx.eval()
     v_o, g_o = prob.oracle()
     tn, tg = TOL[prec]
-    # relative to the magnitude of the summed terms (with the K-K+K+ grid, -2 ln L cancels to ~ -5)
-    assert abs(v - v_o) <= tn * prob.nll_scale(), (v, v_o, prob.nll_scale())
+    if prec == "mixed" and wl is synth.KKK:
+        # relative to the magnitude of the summed terms: with the K-K+K+ grid, -2 ln L cancels to ~ -5
+        # from terms of ~1.5e4
+        assert abs(v - v_o) <= tn * prob.nll_scale(), (v, v_o, prob.nll_scale())
+    else:
+        assert abs(v - v_o) <= tn * abs(v_o), (v, v_o, abs(v - v_o) / abs(v_o))
     n_ck = 2 * wl.n_knots + 2 * wl.n_res
     assert np.abs(g[:n_ck] - g_o[:n_ck]).max() <= tg * np.abs(g_o[:n_ck]).max()
     ctx.close()
@@ -49,7 +53,7 @@ def test_finer_grid_moves_the_likelihood_toward_the_monte_carlo_normalisation():
 
 @pytest.mark.slow
 def test_fit_bias_shrinks_with_the_grid_spacing():
-    """The effect of Fig. 3 on the seeded K-K+K+ toy: fitted knots move toward the input values as the
+    """The effect of Fig. 2 on the seeded K-K+K+ toy: fitted knots move toward the input values as the
     grid spacing falls from 0.01 to 0.001 GeV^2, and at 0.001 their pulls are of order one."""
     import bench
     res = {r["spacing_GeV2"]: r for r in bench.paper_fit("fp64")["fits"]}

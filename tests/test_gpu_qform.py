@@ -23,21 +23,21 @@ def test_quadratic_form_matches_oracle(wl, seed, prec):
     ctx = _ctx(prob, prec)
     v, g = ctx.eval()
     v_o, g_o = prob.oracle()
-    if prec == "fp64":
-        assert rel(v, v_o) <= 1e-10, (v, v_o)
-        tg = 1e-8
-    else:
-        assert abs(v - v_o) <= 1e-6 * prob.nll_scale(), (v, v_o)
-        tg = 1e-4
     n_ck = 2 * wl.n_knots + 2 * wl.n_res
     err = np.abs(g[:n_ck] - g_o[:n_ck])
     if prec == "fp64":
-        assert err.max() <= tg * np.abs(g_o[:n_ck]).max()
+        assert rel(v, v_o) <= 1e-10, (v, v_o)
+        assert err.max() <= 1e-8 * np.abs(g_o[:n_ck]).max()
+    elif wl is not synth.KKK:
+        assert rel(v, v_o) <= 1e-6, (v, v_o, rel(v, v_o))
+        assert err.max() <= 1e-4 * np.abs(g_o[:n_ck]).max(), (err.max(), np.abs(g_o[:n_ck]).max())
     else:
-        # FP32 inputs: relative to the largest component, or to the size of the cancelling terms (an
-        # FP64 emulation of the FP32 inputs and data-side arithmetic gives 5e-6 of it for the
-        # phi(1020) coefficient of K-K+K+, where data and normalisation sums of ~1.7e4 cancel to 245)
-        bound = tg * np.abs(g_o[:n_ck]).max() + 1e-5 * prob.grad_scale()[:n_ck]
+        # K-K+K+ with phi(1020): -2 ln L and the phi coefficient's gradient cancel (data and
+        # normalisation sums of ~1.7e4 to 245), and FP32 rounding of the inputs shared by all points is
+        # coherent across the terms; an FP64 emulation of the FP32 inputs and data-side arithmetic
+        # gives 5e-6 of their size.  Bounds relative to the size of the summed terms.
+        assert abs(v - v_o) <= 1e-6 * prob.nll_scale(), (v, v_o)
+        bound = 1e-4 * np.abs(g_o[:n_ck]).max() + 1e-5 * prob.grad_scale()[:n_ck]
         assert np.all(err <= bound), (np.argmax(err - bound), err.max())
     ctx.close()
 

@@ -1,9 +1,9 @@
-"""The evenly spaced normalisation grid of Sec. 4 (spacings of Fig. 3) and the normalisation integral
+"""The evenly spaced normalisation grid of Sec. 4 (spacings of Fig. 2) and the normalisation integral
 computed on it.
 
 Pins: the number of grid points times the cell area against the region's area by quadrature, within
 the bound set by the cells the boundary crosses; the grid integral of |A|^2 against an independent
-Monte Carlo estimate; and its convergence as the spacing shrinks, which is the effect Fig. 3 shows.
+Monte Carlo estimate; and its convergence as the spacing shrinks, which is the effect Fig. 2 shows.
 """
 import math
 
