@@ -161,6 +161,21 @@ int mipwa_eval(mipwa_ctx* ctx, double* nll, double* grad);
  * non-finite value is not reported as E_DOMAIN (inspect d_out). */
 int mipwa_eval_async(mipwa_ctx* ctx, void* hip_stream, double* d_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the evaluation of mipwa_eval_async, with the same kernels, launch
+ * shape and result, that allocates nothing.  Its scratch -- segment and job descriptors, resonance
+ * constants, the per-block records and the group records -- lives in one static device array of 8 MiB
+ * per GPU (held until the process ends) instead of context buffers; the events, normalisation points,
+ * resonance cache and tables stay those the context allocated when the points were loaded.  At the
+ * default launch shape (2 blocks per CU) every model up to 128 knots and 4 resonances fits.
+ * Every call on one GPU shares that array and it keeps the last call's contents: calls that overlap on
+ * one GPU (from any context, on streams not ordered with each other) race.  Calls on one context are
+ * ordered with its other evaluations like mipwa_eval_async.  d_out: device pointer to 1 + P doubles.
+ * Errors: E_INVAL (d_out NULL; a launch shape whose records exceed the array, see mipwa_set_launch),
+ * E_STATE (nothing loaded, no parameters, or the quadratic-form normalisation, whose per-cell moments
+ * are context memory: use MIPWA_NORM_POINTS), E_HIP. */
+int mipwa_eval_noalloc(mipwa_ctx* ctx, void* hip_stream, double* d_out);
+
 /* Component integrals over the normalisation points (Sec. 2, Eq. 1 components; component 0 = S-wave,
  * r = 1..R the resonances at the current theta): I_jk = sum_p w_p [eff_p] A_j A_k^*, K = R + 1.
  * with_eff = 0 omits the efficiency (for fit fractions).  Ijk receives 2 K K doubles (re, im), row-major. */

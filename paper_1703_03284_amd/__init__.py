@@ -175,6 +175,12 @@ class Context:
         self._check(self._lib.mipwa_eval_async(self._h, C.c_void_p(stream_handle), C.c_void_p(d_out_ptr)),
                     "eval_async")
 
+    def eval_noalloc(self, stream_handle: int, d_out_ptr: int):
+        """As eval_async, with the evaluation's scratch in the library's static per-GPU array: no device
+        memory is allocated (point-sweep normalisation only; calls that overlap on one GPU race)."""
+        self._check(self._lib.mipwa_eval_noalloc(self._h, C.c_void_p(stream_handle), C.c_void_p(d_out_ptr)),
+                    "eval_noalloc")
+
     def timing(self):
         """(device ms of cache+stream+reduce, device ms of the streaming kernel) of the last evaluation."""
         a, b = C.c_double(), C.c_double()

@@ -56,6 +56,7 @@ SIGNATURES = {
     "mipwa_set_params": (C.c_int, [_P, _D, C.c_int]),
     "mipwa_eval": (C.c_int, [_P, _D, _D]),
     "mipwa_eval_async": (C.c_int, [_P, _P, _P]),
+    "mipwa_eval_noalloc": (C.c_int, [_P, _P, _P]),
     "mipwa_integrals": (C.c_int, [_P, C.c_int, _D]),
     "mipwa_fit_fractions": (C.c_int, [_P, _D]),
     "mipwa_fit": (C.c_int, [_P, C.POINTER(FitOptsC), _D, _D, C.POINTER(FitInfoC)]),

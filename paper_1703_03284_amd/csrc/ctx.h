@@ -87,6 +87,16 @@ struct mipwa_ctx {
   int ext_res_off() const { return swave == mipwa::kSwaveIsobar ? 2 : 2 * mh.N; }
   // external theta -> internal (polar spline) theta
   void to_internal(const double* ext, double* internal) const;
+  // grid and record layout of an evaluation: blocks of the data and normalisation streams, record size
+  // and reduction groups
+  struct LaunchPlan {
+    int B = 0, nb_d = 0, nb_n = 0, rs = 0, G_d = 0, G_n = 0, waves = 4;
+  };
+  LaunchPlan plan_launch() const;
+  // segment and job descriptors of the point-sweep evaluation with its records at `records` and its
+  // group records at `grec` (device addresses)
+  void make_segments(const LaunchPlan& L, double* records, mipwa::Segment sg[2]) const;
+  void make_job(const LaunchPlan& L, double* grec, mipwa::Job& jb) const;
   int rebuild_launch();
   int stage_params();
   bool shapes_changed() const;

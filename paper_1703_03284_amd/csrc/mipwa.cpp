@@ -63,47 +63,32 @@ static std::atomic<unsigned long long> g_eval_seq{0};
 
 // ---- device descriptors and tables -----------------------------------------------------------
 
-int mipwa_ctx::rebuild_launch() {
-  mipwa_ctx* ctx = this;
-  // the buffers below are replaced: nothing queued, on any stream, may still use them
-  if (int rc = drain()) return rc;
-  const int waves = waves_cfg ? waves_cfg : 4;
-  waves_eff = waves;
-  const bool qf = use_qform();
-  int B;
-  if (qf) {
+mipwa_ctx::LaunchPlan mipwa_ctx::plan_launch() const {
+  LaunchPlan L;
+  L.waves = waves_cfg ? waves_cfg : 4;
+  if (use_qform()) {
     // the data stream gets the blocks; the cells of the quadratic form a few blocks of ~4 cells per wave
-    nb_d = std::max(1, std::min(blocks_cfg, std::max(1, ev.n_tiles / (2 * waves))));
-    nb_n = std::min(64, std::max(1, (nm.n_cells + 4 * waves - 1) / (4 * waves)));
-    B = nb_d + nb_n;
+    L.nb_d = std::max(1, std::min(blocks_cfg, std::max(1, ev.n_tiles / (2 * L.waves))));
+    L.nb_n = std::min(64, std::max(1, (nm.n_cells + 4 * L.waves - 1) / (4 * L.waves)));
+    L.B = L.nb_d + L.nb_n;
   } else {
     const int total_tiles = ev.n_tiles + nm.n_tiles;
     // up to the configured grid, at least one tile per wave: small point sets spread over as many
     // CUs as they have tiles (one tile per wave measured faster than two for 10 k + 100 k points)
-    B = std::max(2, std::min(blocks_cfg, std::max(2, total_tiles / waves)));
-    nb_d = (int)std::llround((double)B * ev.n_tiles / std::max(total_tiles, 1));
-    nb_d = std::min(std::max(nb_d, 1), B - 1);
-    nb_n = B - nb_d;
+    L.B = std::max(2, std::min(blocks_cfg, std::max(2, total_tiles / L.waves)));
+    L.nb_d = (int)std::llround((double)L.B * ev.n_tiles / std::max(total_tiles, 1));
+    L.nb_d = std::min(std::max(L.nb_d, 1), L.B - 1);
+    L.nb_n = L.B - L.nb_d;
   }
-  n_blocks = B;
-  const int nint = mh.N - 1;
-  rs = record_size(nint, mh.R, otf);
-  const int G_d = n_groups(nb_d), G_n = n_groups(nb_n);
-  HIPCHK(d_records.alloc((size_t)B * rs * sizeof(double)), "records allocation");
-  HIPCHK(d_grec.alloc((size_t)(G_d + G_n) * rs * sizeof(double)), "group records allocation");
-  std::vector<int2> tasks;
-  for (int g = 0; g < G_d; ++g) tasks.push_back(int2{0, g});
-  for (int g = 0; g < G_n; ++g) tasks.push_back(int2{1, g});
-  n_tasks = (int)tasks.size();
-  HIPCHK(d_tasks.alloc(tasks.size() * sizeof(int2)), "task allocation");
-  HIPCHK(hipMemcpy(d_tasks.p, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice), "task upload");
-  std::vector<int2> bs(B);
-  for (int b = 0; b < B; ++b) bs[b] = b < nb_d ? int2{0, b} : int2{1, b - nb_d};
-  HIPCHK(d_block_seg.alloc(B * sizeof(int2)), "block map allocation");
-  HIPCHK(hipMemcpy(d_block_seg.p, bs.data(), B * sizeof(int2), hipMemcpyHostToDevice), "block map upload");
-  Segment sg[2];
-  std::memset(sg, 0, sizeof(sg));
-  PointSet* ps[2] = {&ev, &nm};
+  L.rs = record_size(mh.N - 1, mh.R, otf);
+  L.G_d = n_groups(L.nb_d);
+  L.G_n = n_groups(L.nb_n);
+  return L;
+}
+
+void mipwa_ctx::make_segments(const LaunchPlan& L, double* records, Segment sg[2]) const {
+  std::memset(sg, 0, 2 * sizeof(Segment));
+  const PointSet* ps[2] = {&ev, &nm};
   for (int k = 0; k < 2; ++k) {
     sg[k].tt = ps[k]->tt.p;
     sg[k].ss = ps[k]->ss.p;
@@ -111,16 +96,60 @@ int mipwa_ctx::rebuild_launch() {
     sg[k].cache = ps[k]->cache.p;
     sg[k].tiles = ps[k]->tiles.as<Tile>();
     sg[k].table = use_arg ? nullptr : d_blob.p;
-    sg[k].records = d_records.as<double>() + (size_t)(k ? nb_d : 0) * rs;
+    sg[k].records = records + (size_t)(k ? L.nb_d : 0) * L.rs;
     sg[k].n = ps[k]->n;
     sg[k].n_tiles = ps[k]->n_tiles;
     sg[k].kind = k;
-    sg[k].nint = nint;
-    sg[k].rs = rs;
-    sg[k].n_blocks = k ? nb_n : nb_d;
+    sg[k].nint = mh.N - 1;
+    sg[k].rs = L.rs;
+    sg[k].n_blocks = k ? L.nb_n : L.nb_d;
     sg[k].job = 0;
-    sg[k].g0 = k ? G_d : 0;
+    sg[k].g0 = k ? L.G_d : 0;
   }
+}
+
+void mipwa_ctx::make_job(const LaunchPlan& L, double* grec, Job& jb) const {
+  std::memset(&jb, 0, sizeof(jb));
+  jb.tab64 = use_arg ? nullptr : d_blob.as<double>() + tab64_off / sizeof(double);
+  jb.theta_off = arg_theta_off;
+  jb.consts = d_blob.as<double>() + consts_off / sizeof(double);
+  jb.grec = grec;
+  jb.n_ev = (double)ev.n;
+  jb.c_eps = ev.c_eps;
+  jb.G_d = L.G_d;
+  jb.G_n = L.G_n;
+  jb.N = mh.N;
+  jb.R = mh.R;
+  jb.rs = L.rs;
+  jb.otf = otf ? 1 : 0;
+  jb.swave = swave;
+}
+
+int mipwa_ctx::rebuild_launch() {
+  mipwa_ctx* ctx = this;
+  // the buffers below are replaced: nothing queued, on any stream, may still use them
+  if (int rc = drain()) return rc;
+  const LaunchPlan L = plan_launch();
+  waves_eff = L.waves;
+  nb_d = L.nb_d;
+  nb_n = L.nb_n;
+  n_blocks = L.B;
+  rs = L.rs;
+  const bool qf = use_qform();
+  HIPCHK(d_records.alloc((size_t)L.B * L.rs * sizeof(double)), "records allocation");
+  HIPCHK(d_grec.alloc((size_t)(L.G_d + L.G_n) * L.rs * sizeof(double)), "group records allocation");
+  std::vector<int2> tasks;
+  for (int g = 0; g < L.G_d; ++g) tasks.push_back(int2{0, g});
+  for (int g = 0; g < L.G_n; ++g) tasks.push_back(int2{1, g});
+  n_tasks = (int)tasks.size();
+  HIPCHK(d_tasks.alloc(tasks.size() * sizeof(int2)), "task allocation");
+  HIPCHK(hipMemcpy(d_tasks.p, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice), "task upload");
+  std::vector<int2> bs(L.B);
+  for (int b = 0; b < L.B; ++b) bs[b] = b < L.nb_d ? int2{0, b} : int2{1, b - L.nb_d};
+  HIPCHK(d_block_seg.alloc(L.B * sizeof(int2)), "block map allocation");
+  HIPCHK(hipMemcpy(d_block_seg.p, bs.data(), L.B * sizeof(int2), hipMemcpyHostToDevice), "block map upload");
+  Segment sg[2];
+  make_segments(L, d_records.as<double>(), sg);
   std::memcpy(h_segs, sg, sizeof(sg));  // the point streams: cache builds and the moment pass use them
   if (qf) {
     const int K = qform_dim(mh.R);
@@ -136,23 +165,7 @@ int mipwa_ctx::rebuild_launch() {
   // job 0 writes the results into mapped pinned host memory (synchronous evaluations), job 1 into
   // device memory (asynchronous evaluations, copied to the caller's buffer on its stream)
   Job jb[2];
-  std::memset(jb, 0, sizeof(jb));
-  for (int k = 0; k < 2; ++k) {
-    const double* t64 = d_blob.as<double>() + tab64_off / sizeof(double);
-    jb[k].tab64 = use_arg ? nullptr : t64;
-    jb[k].theta_off = arg_theta_off;
-    jb[k].consts = d_blob.as<double>() + consts_off / sizeof(double);
-    jb[k].grec = d_grec.as<double>();
-    jb[k].n_ev = (double)ev.n;
-    jb[k].c_eps = ev.c_eps;
-    jb[k].G_d = G_d;
-    jb[k].G_n = G_n;
-    jb[k].N = mh.N;
-    jb[k].R = mh.R;
-    jb[k].rs = rs;
-    jb[k].otf = otf ? 1 : 0;
-    jb[k].swave = swave;
-  }
+  for (int k = 0; k < 2; ++k) make_job(L, d_grec.as<double>(), jb[k]);
   jb[0].out = h_out_dev;
   jb[0].seq_out = reinterpret_cast<unsigned long long*>(h_out_dev + 1 + mh.P);
   jb[1].out = d_out.as<double>();
