@@ -5,8 +5,9 @@ the truth parameters, 10M uniform phase-space normalisation points, 50 S-wave kn
 f2(1270), efficiency from a 200x200 FP32 table; mixed precision (FP32 streams and amplitudes, FP64
 accumulation and finish).  One step = one full evaluation (parameter upload, spline setup, the
 streaming forward+adjoint kernel over both point sets, reduction, FP64 finish, result readback).
-The plain FP64 GPU path is timed on the same workload and reported beside it, and the FP64 oracle is
-timed on a bounded sample on the host (cpu_baseline).
+The plain FP64 GPU path is timed on the same workload and reported beside it; the FP64 oracle evaluates
+the same inputs on the host's cores (cpu_baseline) and the mixed-precision results are stated against
+it (vs_oracle).
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cpu] [--no-fp64]
 """
@@ -30,29 +31,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def algorithmic_bytes_per_point(precision_bytes: int, kind: str) -> int:
+    """Bytes the method must read per point and evaluation: its two coordinates (t12, t13) and, for a
+    normalisation point, its weight x efficiency."""
+    return 2 * precision_bytes + (precision_bytes if kind == "norm" else 0)
+
+
 def stream_bytes_per_point(precision_bytes: int, n_res: int, kind: str) -> int:
-    """Bytes the streaming kernel must read per point: (t12, t13) + one complex amplitude per resonance
-    (+ the weight for normalisation points)."""
-    b = 2 * precision_bytes + 2 * n_res * precision_bytes
-    return b + (precision_bytes if kind == "norm" else 0)
+    """Bytes the streaming kernel reads per point by design: the algorithmic bytes plus the cached
+    symmetrised amplitude of each resonance (one complex number)."""
+    return algorithmic_bytes_per_point(precision_bytes, kind) + 2 * n_res * precision_bytes
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_eval_mixed_10M_traffic.md")
+TRAFFIC_PROFILE_FP64 = os.path.join(ROOT, "profiles", "k_eval_fp64_10M_kernel_trace_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1703_03284_amd", "csrc", "kernels.hip")
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the streaming kernel from the committed counter summary (FETCH_SIZE +
+def recorded_traffic(path):
+    """HBM bytes per launch of the streaming kernel from a committed counter summary (FETCH_SIZE +
     WRITE_SIZE, each scaled by a 1 GiB copy), or None once the kernel source differs from the one
     the counters were taken on."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
     except OSError:
         return None
     fields = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(" "))
     src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("Kernel source sha256 (csrc/kernels.hip)", "").strip() != src:
+    if fields.get("Kernel source sha256 (csrc/kernels.hip)", "").strip() != src or \
+            "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -112,65 +120,116 @@ def time_gpu(wl, precision, table, events, norm, steps, warmup, blocks=0, waves=
     wall = time.perf_counter() - t0
     n_timed, dev_ms, stream_ms = ctx.timing_stats()
     ctx.set_timing(False)
-    nll, _ = ctx.eval(th0)
+    nll, grad = ctx.eval(th0)
+    ff = None if wl.float_shapes else ctx.fit_fractions(th0)
     ctx.close()
     assert n_timed == steps
     return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "value": steps / wall,
-            "dev_ms": dev_ms, "stream_kernel_ms": stream_ms, "nll": nll}
+            "dev_ms": dev_ms, "stream_kernel_ms": stream_ms, "nll": nll, "grad": grad, "ff": ff}
 
 
-_CPU_DATA = {}
-
-
-def _oracle_chunk(args):
-    """One chunk of the oracle's -2 ln L + gradient over the shared sample (set up before the pool forks)."""
+def oracle_leg(wl, table, events, norm, mixed, reps=1):
+    """The FP64 oracle on the headline inputs themselves (the same toy events, normalisation points
+    and efficiency table as the GPU run), split in 1M-point chunks over worker processes on the host's
+    cores: one evaluation that also warms the workers up, then `reps` timed evaluations (the CPU
+    baseline).  Compares the mixed-precision library's -2 ln L, gradient and fit fractions at the same
+    point with the oracle's; the gradient error is also weighted by the errors sigma_p of a fit of this
+    sample, taken from the expected information (oracle, 200k-point subsample)."""
     from threadpoolctl import threadpool_limits
-    from oracle import likelihood as L
-    idx, n_chunks = args
-    m, th, ev, nm = _CPU_DATA["m"], _CPU_DATA["th"], _CPU_DATA["ev"], _CPU_DATA["nm"]
-    n = len(ev[0])
-    lo, hi = idx * n // n_chunks, (idx + 1) * n // n_chunks
-    with threadpool_limits(limits=1):
-        return L.nll_and_grad(m, th, (ev[0][lo:hi], ev[1][lo:hi]),
-                              (nm[0][lo:hi], nm[1][lo:hi], nm[2][lo:hi]), shapes=False)
-
-
-def cpu_baseline(n_events, n_norm, sample=2_000_000, reps=3):
-    """The oracle, as it is, on a bounded sample of the headline workload (sample events + sample
-    normalisation points): once in one process (1 core), once split in chunks over a process pool on
-    every host core.  Runs before any GPU work (the pool forks)."""
-    import multiprocessing as mp
-    import synth
     from oracle import Model, Res
-    from oracle import kinematics as K
-    wl = synth.C3
+    from oracle import likelihood as L
+    from oracle.pool import OraclePool
     d = wl.decay
     m = Model(d.M, d.m1, d.m2, d.m3, d.rD, tuple(wl.knots()),
               tuple(Res(r.spin, r.mass, r.width, r.radius) for r in wl.resonances))
-    s12, s13 = synth.uniform_phase_space(d, sample, 2)
-    _CPU_DATA.update(m=m, th=wl.start(), ev=synth.uniform_phase_space(d, sample, 1),
-                     nm=(s12, s13, np.full(sample, K.area(m) / sample)))
-    scale = (n_events + n_norm) / (2 * sample)
-    one = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        _oracle_chunk((0, 1))
-        one.append(time.perf_counter() - t0)
-    t1 = float(np.median(one))
-    cores = min(len(os.sched_getaffinity(0)), 64)
-    with mp.get_context("fork").Pool(cores) as pool:
-        alls = []
+    th = wl.start()
+    n12, n13, w = norm
+    e_ev = L.hist_lookup(table, d.smin, d.smax, *events) if table is not None else np.ones(len(events[0]))
+    e_nm = L.hist_lookup(table, d.smin, d.smax, n12, n13) if table is not None else np.ones(len(n12))
+    t0 = time.perf_counter()
+    pool = OraclePool(m, events, (n12, n13, w * e_nm), float(np.sum(np.log(e_ev))), w_plain=w)
+    try:
+        log(f"[bench] oracle: {pool.workers} worker processes, arrays mapped in {time.perf_counter() - t0:.1f}s")
+        v_o, g_o = pool.nll_and_grad(th)
+        times = []
         for _ in range(reps):
             t0 = time.perf_counter()
-            pool.map(_oracle_chunk, [(i, cores) for i in range(cores)])
-            alls.append(time.perf_counter() - t0)
-    tn = float(np.median(alls))
-    _CPU_DATA.clear()
-    return {"value": 1.0 / (tn * scale), "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{sample} events + {sample} normalisation points of the headline workload, "
-                      f"split over {cores} processes, median of {reps}, scaled x{scale:.0f} to "
-                      f"{n_events} + {n_norm} points; {tn:.2f} s per sample evaluation",
-            "one_core": {"value": 1.0 / (t1 * scale), "cores": 1, "seconds_per_sample_eval": t1}}
+            pool.nll_and_grad(th)
+            times.append(time.perf_counter() - t0)
+        t_all = float(np.median(times))
+        free = np.flatnonzero(wl.fixed() == 0)
+        sigma = pool.expected_sigma(th, free, 200_000)
+        ff_o = L.fit_fractions(m, th, pool.integrals(th))
+        workers = pool.workers
+    finally:
+        pool.close()
+    # one core: the same oracle on one 1M + 1M chunk in this process, scaled to the full inputs
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        L.point_sums(m, th, events[0][:1_000_000], events[1][:1_000_000], None, False)
+        L.point_sums(m, th, n12[:1_000_000], n13[:1_000_000], (w * e_nm)[:1_000_000], False)
+        t1 = (time.perf_counter() - t0) * (len(events[0]) + len(n12)) / 2_000_000
+    n_ck = 2 * wl.n_knots + 2 * wl.n_res
+    v, g, ff = mixed["nll"], mixed["grad"], mixed["ff"]
+    dg = np.abs(g[:n_ck] - g_o[:n_ck])
+    vs = {"point": "the start point of the fits (truth perturbed)",
+          "nll": v, "nll_oracle": v_o, "nll_abs": abs(v - v_o), "nll_rel": abs(v - v_o) / abs(v_o),
+          "grad_rel_inf": float(dg.max() / np.abs(g_o[:n_ck]).max()),
+          "grad_sigma_weighted": float(np.max(dg[free[free < n_ck]] * sigma[free[free < n_ck]])),
+          "ff_abs_max": float(np.abs(np.diag(ff) - np.diag(ff_o)).max()),
+          "ff_oracle": [float(x) for x in np.diag(ff_o)]}
+    cpu = {"value": 1.0 / t_all, "unit": "evals/s", "cores": workers, "kind": "oracle",
+           "sample": f"the full headline inputs ({len(events[0])} toy events + {len(n12)} normalisation points, "
+                     f"the same arrays as the GPU run), -2 ln L + knot and coefficient gradient, split in 1M-point "
+                     f"chunks over {workers} worker processes, median of {reps} after one warm-up evaluation; "
+                     f"{t_all:.2f} s per evaluation",
+           "one_core": {"value": 1.0 / t1, "cores": 1, "seconds_per_eval": t1,
+                        "how": "one 1M + 1M chunk in one process, scaled to the full inputs"}}
+    return cpu, vs
+
+
+def small_fit_vs_oracle():
+    """The 10k-event fit workload fitted by the library in mixed precision and by the oracle (scipy
+    BFGS, V = 2 H^-1) from the same start on the same toy: the largest |d theta| / sigma over the
+    floated parameters, the spread of the error ratio and of the fit-fraction difference."""
+    import synth
+    from oracle import fit as OF
+    from oracle import generate as OG
+    from oracle import kinematics as K
+    from oracle import likelihood as L
+    from oracle import Model, Res
+    from paper_1703_03284_amd import MIXED, context_for
+    wl = synth.C1
+    d = wl.decay
+    m = Model(d.M, d.m1, d.m2, d.m3, d.rD, tuple(wl.knots()),
+              tuple(Res(r.spin, r.mass, r.width, r.radius) for r in wl.resonances))
+    s12, s13, _ = OG.toy(m, wl.truth(), wl.n_events, seed=wl.seed("events"), n_probe=200_000)
+    n12, n13 = synth.uniform_phase_space(d, wl.n_norm, wl.seed("norm"))
+    norm = (n12, n13, np.full(len(n12), K.area(m) / len(n12)))
+    t0 = time.perf_counter()
+    ref = OF.fit(m, wl.start(), (s12, s13), norm, wl.fixed(), gtol=1e-6)
+    t_oracle = time.perf_counter() - t0
+    ctx = context_for(d, wl.knots(), wl.resonances, MIXED)
+    ctx.load_events(s12, s13)
+    ctx.load_norm(*norm)
+    t0 = time.perf_counter()
+    res = ctx.fit(wl.start(), fixed=wl.fixed(), tol_edm=1e-8)
+    t_lib = time.perf_counter() - t0
+    ff = np.diag(ctx.fit_fractions(res.theta))
+    ctx.close()
+    free = np.flatnonzero(wl.fixed() == 0)
+    dth = res.theta - ref["theta"]
+    npair = wl.n_knots + wl.n_res
+    dth[1:2 * npair:2] = np.angle(np.exp(1j * dth[1:2 * npair:2]))
+    ratio = res.sigma[free] / ref["sigma"][free]
+    ff_o = np.diag(L.fit_fractions(m, ref["theta"], L.integrals(m, ref["theta"], norm)))
+    return {"workload": f"D+->pi-pi+pi+ {wl.n_events} toy events + {wl.n_norm} normalisation points, "
+                        f"{wl.n_knots} knots, rho(770)+f2(1270), {len(free)} floated parameters",
+            "precision": "mixed", "fit_theta_max_sigma": float(np.max(np.abs(dth[free]) / ref["sigma"][free])),
+            "sigma_ratio_min": float(ratio.min()), "sigma_ratio_max": float(ratio.max()),
+            "ff_abs_max": float(np.abs(ff - ff_o).max()), "nll_abs": abs(res.nll - ref["nll"]),
+            "library_fit_s": round(t_lib, 3), "oracle_fit_s": round(t_oracle, 1), "evals": res.n_eval,
+            "status": res.status}
 
 
 def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
@@ -394,26 +453,38 @@ def main():
     if args.profile_pass:
         profile_pass(args.steps, args.profile_pass)
         return
-    n_ev_cpu = args.events or 10_000_000
-    n_nm_cpu = args.norm or 10_000_000
-    cpu = None if args.no_cpu else cpu_baseline(n_ev_cpu, n_nm_cpu)  # before any GPU work (fork)
-    if cpu:
-        log(f"[bench] cpu baseline: {cpu}")
     import synth
-    from paper_1703_03284_amd import FP64, MIXED
+    from paper_1703_03284_amd import FP64, MIXED, read_bandwidth
     wl = synth.C3
     n_ev = args.events or wl.n_events
     n_nm = args.norm or wl.n_norm
     table, events, norm = build_inputs(wl, n_ev, n_nm)
     mixed = time_gpu(wl, MIXED, table, events, norm, args.steps, args.warmup, args.blocks, args.waves)
-    log(f"[bench] mixed: {mixed}")
+    log(f"[bench] mixed: { {k: v for k, v in mixed.items() if k not in ('grad', 'ff')} }")
     fp64 = None
     if not args.no_fp64:
         fp64 = time_gpu(wl, FP64, table, events, norm, args.steps, args.warmup, args.blocks, args.waves)
-        log(f"[bench] fp64: {fp64}")
-    bytes_launch = n_ev * stream_bytes_per_point(4, wl.n_res, "data") + \
-        n_nm * stream_bytes_per_point(4, wl.n_res, "norm")
-    achieved = bytes_launch / (mixed["stream_kernel_ms"] * 1e-3) / 1e9
+        log(f"[bench] fp64: { {k: v for k, v in fp64.items() if k not in ('grad', 'ff')} }")
+    ceiling = read_bandwidth(0, 1 << 30, 10)
+    log(f"[bench] measured streaming-read ceiling: {ceiling:.0f} GB/s")
+
+    def roof(prec_bytes, kernel_ms, kernel, traffic):
+        alg = n_ev * algorithmic_bytes_per_point(prec_bytes, "data") + n_nm * algorithmic_bytes_per_point(prec_bytes, "norm")
+        des = n_ev * stream_bytes_per_point(prec_bytes, wl.n_res, "data") + \
+            n_nm * stream_bytes_per_point(prec_bytes, wl.n_res, "norm")
+        sec = kernel_ms * 1e-3
+        r = {"bound": "hbm", "achieved": alg / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": alg / sec / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+             "kernel": kernel, "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": alg,
+             "design_bytes_per_launch": des, "design_achieved": des / sec / 1e9,
+             "design_frac": des / sec / 1e9 / HBM_PEAK_GBS,
+             "measured_read_ceiling_GBs": ceiling, "design_frac_of_measured_ceiling": des / sec / 1e9 / ceiling}
+        if traffic is not None:
+            r["traffic_over_algorithmic"] = traffic / alg
+            r["traffic_over_design"] = traffic / des
+        return r
+
+    full = (n_ev, n_nm) == (wl.n_events, wl.n_norm)
     out = {
         "metric": "NLL+grad evals/sec @10M events (mixed vs FP64 GPU); toy fits/sec + p50/p99",
         "value": mixed["value"],
@@ -435,12 +506,11 @@ def main():
         "fp64": None if fp64 is None else {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
                                            "device_ms_per_step": fp64["dev_ms"],
                                            "stream_kernel_ms": fp64["stream_kernel_ms"],
-                                           "mixed_speedup": mixed["value"] / fp64["value"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic() if (n_ev, n_nm) == (wl.n_events, wl.n_norm) else None,
-                     "kernel": "k_eval<float,2,false>", "bytes_per_launch": bytes_launch,
-                     "kernel_ms": mixed["stream_kernel_ms"]},
+                                           "mixed_speedup": mixed["value"] / fp64["value"],
+                                           "roofline": roof(8, fp64["stream_kernel_ms"], "k_eval<double,2,false>",
+                                                            recorded_traffic(TRAFFIC_PROFILE_FP64) if full else None)},
+        "roofline": roof(4, mixed["stream_kernel_ms"], "k_eval<float,2,false>",
+                         recorded_traffic(TRAFFIC_PROFILE) if full else None),
     }
     # the same evaluation with the normalisation as a quadratic form over per-cell moments (an
     # algebraic rearrangement beyond the paper; reported beside the headline, not as it)
@@ -469,7 +539,12 @@ def main():
         out["serving"] = serving(args.serve_jobs, MIXED)
     if not args.no_paper_fit:
         out["paper_fit"] = paper_fit("fp64")
-    if cpu:
+    if not args.no_cpu:
+        cpu, vs = oracle_leg(wl, table, events, norm, mixed)
+        log(f"[bench] oracle on the headline inputs: {cpu}; {vs}")
+        vs["small_fit"] = small_fit_vs_oracle()
+        log(f"[bench] small fit against the oracle's: {vs['small_fit']}")
+        out["vs_oracle"] = vs
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 

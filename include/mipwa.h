@@ -242,6 +242,12 @@ int mipwa_last_timing(const mipwa_ctx* ctx, double* total_ms, double* stream_ms)
  * evaluations and the mean device time of the whole evaluation (upload to finish) and of the
  * streaming kernel alone, in milliseconds. */
 int mipwa_set_timing(mipwa_ctx* ctx, int on);
+
+/* Measured streaming-read ceiling of a GPU, the denominator beside the datasheet peak when the
+ * likelihood sweep's bandwidth is reported: a buffer of `bytes` (>= 1 MiB) is read with 16-byte
+ * non-temporal loads and no other work, `reps` times after one warm-up; *gbs receives the best rate in
+ * GB/s.  Allocates and frees its own buffer.  Errors: E_INVAL, E_NOMEM, E_HIP. */
+int mipwa_read_bandwidth(int device, int64_t bytes, int reps, double* gbs);
 int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_ms, double* mean_stream_ms);
 
 /* Launch shape of the streaming kernel: blocks (0 = default) and waves per block (0 = default, 1..16).

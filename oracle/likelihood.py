@@ -127,27 +127,40 @@ def _to_params(model, theta, gz, gc, gshape):
     return out
 
 
+def point_sums(model, theta, s12, s13, w=None, shapes=True):
+    """The sums over one set of points that -2 ln L and its gradient are made of: for data points
+    (w None) sum ln|A|^2 and the complex partials with the seed -4A/|A|^2; for normalisation points
+    of weight w (x efficiency) sum w|A|^2 and the partials with the seed 4 w A, before the n / I scale.
+    Returns (gz, gc, gshape, sum).  Sums over disjoint subsets of the points add up to the sums over
+    their union."""
+    if w is None:
+        def seed(a, lo, hi):
+            aa = a.real ** 2 + a.imag ** 2
+            return -4.0 * a / aa, float(np.sum(np.log(aa)))
+    else:
+        def seed(a, lo, hi):
+            return 4.0 * w[lo:hi] * a, float(np.sum(w[lo:hi] * (a.real ** 2 + a.imag ** 2)))
+    return _accumulate(model, theta, s12, s13, seed, shapes)
+
+
+def combine(model, theta, n_events, data_sums, norm_sums, log_eps_sum=0.0):
+    """(-2 ln L, gradient) from the data and normalisation point sums of point_sums:
+    -2 ln L = -2 sum ln|A|^2 - 2 sum ln eps + 2 n ln I, gradient = data partials + (n / I) norm partials."""
+    gz_d, gc_d, gs_d, sum_log = data_sums
+    gz_n, gc_n, gs_n, I = norm_sums
+    scale = n_events / I
+    value = -2.0 * sum_log - 2.0 * log_eps_sum + 2.0 * n_events * np.log(I)
+    grad = _to_params(model, theta, gz_d + scale * gz_n, gc_d + scale * gc_n, gs_d + scale * gs_n)
+    return value, grad
+
+
 def nll_and_grad(model, theta, events, norm, log_eps_sum=0.0, shapes=True):
     """(-2 ln L, gradient over all 2N + 4R parameters).  With shapes=False the mass and width
     partials are left at zero (they are the expensive part of this reference)."""
     s12, s13 = events
-    n = len(s12)
-
-    def data_seed(a, lo, hi):
-        aa = a.real ** 2 + a.imag ** 2
-        return -4.0 * a / aa, float(np.sum(np.log(aa)))
-
     ns12, ns13, w = norm
-
-    def norm_seed(a, lo, hi):
-        return 4.0 * w[lo:hi] * a, float(np.sum(w[lo:hi] * (a.real ** 2 + a.imag ** 2)))
-
-    gz_d, gc_d, gs_d, sum_log = _accumulate(model, theta, s12, s13, data_seed, shapes)
-    gz_n, gc_n, gs_n, I = _accumulate(model, theta, ns12, ns13, norm_seed, shapes)
-    scale = n / I
-    value = -2.0 * sum_log - 2.0 * log_eps_sum + 2.0 * n * np.log(I)
-    grad = _to_params(model, theta, gz_d + scale * gz_n, gc_d + scale * gc_n, gs_d + scale * gs_n)
-    return value, grad
+    return combine(model, theta, len(s12), point_sums(model, theta, s12, s13, None, shapes),
+                   point_sums(model, theta, ns12, ns13, w, shapes), log_eps_sum)
 
 
 def integrals(model, theta, norm):

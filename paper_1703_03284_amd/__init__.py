@@ -252,6 +252,16 @@ class Context:
         return s12, s13, fmax.value
 
 
+def read_bandwidth(device=0, nbytes=1 << 30, reps=10) -> float:
+    """Measured streaming-read ceiling of the GPU in GB/s (mipwa_read_bandwidth)."""
+    lib = L.load()
+    out = C.c_double()
+    rc = lib.mipwa_read_bandwidth(int(device), int(nbytes), int(reps), C.byref(out))
+    if rc != 0:
+        raise MipwaError(rc, "mipwa_read_bandwidth")
+    return out.value
+
+
 def context_for(decay, knots, resonances, precision=FP64, device=0) -> Context:
     """Context from any object with M, m1, m2, m3, rD attributes and resonance objects with spin, mass,
     width, radius attributes."""

@@ -67,6 +67,7 @@ SIGNATURES = {
     "mipwa_last_timing": (C.c_int, [_P, _D, _D]),
     "mipwa_set_launch": (C.c_int, [_P, C.c_int, C.c_int]),
     "mipwa_set_timing": (C.c_int, [_P, C.c_int]),
+    "mipwa_read_bandwidth": (C.c_int, [C.c_int, _I64, C.c_int, _D]),
     "mipwa_timing_stats": (C.c_int, [_P, C.POINTER(_I64), _D, _D]),
     "mipwa_server_create": (C.c_int, [C.c_int, C.c_int, C.c_size_t, C.POINTER(_P)]),
     "mipwa_server_set_norm": (C.c_int, [_P, _D, _D, _D, _I64]),

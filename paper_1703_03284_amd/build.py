@@ -20,7 +20,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmipwa.so")
-SOURCES = ["kernels.hip", "loader.hip", "noalloc.hip", "host.cpp", "mipwa.cpp", "gen.cpp", "fit.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "loader.hip", "noalloc.hip", "probe.hip", "host.cpp", "mipwa.cpp", "gen.cpp", "fit.cpp", "serve.cpp"]
 ARCH = os.environ.get("MIPWA_OFFLOAD_ARCH", "gfx950")
 
 
