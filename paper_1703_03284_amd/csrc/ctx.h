@@ -58,6 +58,10 @@ struct mipwa_ctx {
   // host-side replacement of those buffers first waits for it.
   hipEvent_t ev_done = nullptr;
   hipStream_t last_st = nullptr;
+  // ascending or descending order of the parts each wave of the point sweep reads; alternates per
+  // evaluation
+  int sweep_order = 0;
+  int sweep_parts_eff = 1;
   hipEvent_t ev_t[2][4] = {};
   int ev_cur = 0;                 // set the next timed evaluation records into
   int ev_last = 0;                // set of the last timed evaluation
@@ -91,6 +95,7 @@ struct mipwa_ctx {
   // and reduction groups
   struct LaunchPlan {
     int B = 0, nb_d = 0, nb_n = 0, rs = 0, G_d = 0, G_n = 0, waves = 4;
+    int parts = 1;  // parts of each wave's tile range in the point sweep (launch_eval)
   };
   LaunchPlan plan_launch() const;
   // segment and job descriptors of the point-sweep evaluation with its records at `records` and its

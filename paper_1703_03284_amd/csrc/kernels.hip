@@ -211,9 +211,12 @@ __global__ __launch_bounds__(256) void k_cache(Segment sg, const double* __restr
 // ---------------------------------------------------------------------------------------------
 // K2: fused forward + adjoint over the tiles of one segment, persistent waves.
 
+// bins: this wave's `parts` interval histograms, stride doubles apart; scal: its `parts` sets of nsc
+// scalars.  order 0 / 1: the parts of the wave's tile range are swept in ascending / descending order.
 template <typename Real, int R, bool OTF, int KIND>
 __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& kin, const Real* tab, double* bins,
-                                            double* scal, int wave, int lane, int waves, int local_block) {
+                                            double* scal, int wave, int lane, int waves, int local_block, int stride,
+                                            int parts, int order) {
   using O = Ops<Real>;
   using V2 = typename O::V2;
   constexpr int R1 = R > 0 ? R : 1;
@@ -259,6 +262,7 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   Real p12[8], p13[8];
 #pragma unroll
   for (int m = 0; m < 8; ++m) p12[m] = p13[m] = Real(0);
+  double* hb = bins;  // interval histogram of the part being swept
 
   auto flush = [&]() {
 #pragma unroll
@@ -274,8 +278,8 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
       q12[m] = 0.0;
       q13[m] = 0.0;
       if (lane == 0) {
-        bins[8 * cj12 + m] += a;
-        bins[8 * cj13 + m] += b;
+        hb[8 * cj12 + m] += a;
+        hb[8 * cj13 + m] += b;
       }
     }
   };
@@ -377,6 +381,63 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     }
   };
 
+  // Closes the sweep of part h of the wave's tiles: flushes the cell in progress, folds the running
+  // sums of the FP64 streams, and stores the wave's reduced scalars in slot h; the accumulators start
+  // again from zero.
+  const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
+  auto end_half = [&](int h) {
+    if constexpr (!kTilePartial) {
+      acc += (double)tacc;
+      tacc = Real(0);
+#pragma unroll
+      for (int r = 0; r < 2 * R; ++r) {
+        agc[r] += (double)tgc[r];
+        tgc[r] = Real(0);
+        if constexpr (OTF) {
+          ahm[r] += (double)thm[r];
+          ahg[r] += (double)thg[r];
+          thm[r] = thg[r] = Real(0);
+        }
+      }
+    }
+    if (cj12 >= 0) flush();
+    cj12 = cj13 = -1;
+    if constexpr (OTF) {
+      // g conj(dR/dm) = dlk g conj(R) - 2 m g conj(E) - i ddm g conj(F),  g conj(dR/dGamma) = -i ddg g conj(F)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const Real* c = res + r * kResWords;
+        const double m2 = 2.0 * (double)c[5], dlk = (double)c[6], ddm = (double)c[7], ddg = (double)c[8];
+        const double er = ahm[2 * r], ei = ahm[2 * r + 1], fr = ahg[2 * r], fi = ahg[2 * r + 1];
+        ahm[2 * r] = dlk * agc[2 * r] - m2 * er + ddm * fi;
+        ahm[2 * r + 1] = dlk * agc[2 * r + 1] - m2 * ei - ddm * fr;
+        ahg[2 * r] = ddg * fi;
+        ahg[2 * r + 1] = -ddg * fr;
+      }
+    }
+    double* my = scal + h * nsc;
+    {
+      const double v = wave_sum(acc);
+      if (lane == 0) my[0] = v;
+      acc = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 2 * R; ++r) {
+      const double v = wave_sum(agc[r]);
+      if (lane == 0) my[1 + r] = v;
+      agc[r] = 0.0;
+      if constexpr (OTF) {
+        const double a = wave_sum(ahm[r]);
+        const double b = wave_sum(ahg[r]);
+        if (lane == 0) {
+          my[1 + 2 * R + r] = a;
+          my[1 + 4 * R + r] = b;
+        }
+        ahm[r] = ahg[r] = 0.0;
+      }
+    }
+  };
+
   if constexpr (!OTF) {
     // Cached amplitudes: the sweep is bound by HBM reads (non-temporal loads), so every step keeps
     // loads in flight.  A tile is taken in two halves of HB points per lane; the loads of the next
@@ -420,23 +481,36 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
                    valid);
       }
     };
-    if (t0 < t1) {
+    // The wave's tiles are swept as `parts` equal consecutive parts, each with its own accumulators and
+    // interval histogram, combined in a fixed order at the end: the result does not depend on the
+    // order the parts are taken in.  Consecutive evaluations alternate ascending and descending part
+    // order, so each starts on the parts the previous one read last, while they are still in the
+    // Infinity Cache.
+    auto sweep = [&](int a0, int a1) {
+      if (a0 >= a1) return;
       Half a, b;
       const ConstTiles tiles = (ConstTiles)uniform_ptr(sg.tiles);
-      Tile td = load_tile(tiles, t0);
+      Tile td = load_tile(tiles, a0);
       load_half(a, td, 0);
 #pragma unroll 1
-      for (int ti = t0; ti < t1; ++ti) {
-        // the next descriptor (clamped to this wave's last tile) is requested a tile ahead
-        const Tile tn = load_tile(tiles, min(ti + 1, t1 - 1));
+      for (int ti = a0; ti < a1; ++ti) {
+        // the next descriptor (clamped to this part's last tile) is requested a tile ahead
+        const Tile tn = load_tile(tiles, min(ti + 1, a1 - 1));
         load_half(b, td, 1);
         enter_cell(td.j12, td.j13);
         use_half(a, td, 0);
-        if (ti + 1 < t1) load_half(a, tn, 0);
+        if (ti + 1 < a1) load_half(a, tn, 0);
         use_half(b, td, 1);
         fold_tile();
         td = tn;
       }
+    };
+#pragma unroll 1
+    for (int pass = 0; pass < parts; ++pass) {
+      const int h = order ? parts - 1 - pass : pass;
+      hb = bins + h * stride;
+      sweep(t0 + (int)((long long)(t1 - t0) * h / parts), t0 + (int)((long long)(t1 - t0) * (h + 1) / parts));
+      end_half(h);
     }
   } else {
     // Shapes floated: amplitudes and their derivatives on the fly.  ALU-bound; one point per lane
@@ -485,54 +559,9 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
         tn = sg.tiles[min(ti + 2, t1 - 1)];
       }
     }
-  }
-  if constexpr (!kTilePartial) {
-    acc += (double)tacc;
-#pragma unroll
-    for (int r = 0; r < 2 * R; ++r) {
-      agc[r] += (double)tgc[r];
-      if constexpr (OTF) {
-        ahm[r] += (double)thm[r];
-        ahg[r] += (double)thg[r];
-      }
-    }
-  }
-  if (cj12 >= 0) flush();
-  if constexpr (OTF) {
-    // g conj(dR/dm) = dlk g conj(R) - 2 m g conj(E) - i ddm g conj(F),  g conj(dR/dGamma) = -i ddg g conj(F)
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const Real* c = res + r * kResWords;
-      const double m2 = 2.0 * (double)c[5], dlk = (double)c[6], ddm = (double)c[7], ddg = (double)c[8];
-      const double er = ahm[2 * r], ei = ahm[2 * r + 1], fr = ahg[2 * r], fi = ahg[2 * r + 1];
-      ahm[2 * r] = dlk * agc[2 * r] - m2 * er + ddm * fi;
-      ahm[2 * r + 1] = dlk * agc[2 * r + 1] - m2 * ei - ddm * fr;
-      ahg[2 * r] = ddg * fi;
-      ahg[2 * r + 1] = -ddg * fr;
-    }
-  }
-
-  const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
-  double* my = scal + wave * nsc;
-  {
-    const double v = wave_sum(acc);
-    if (lane == 0) my[0] = v;
-  }
-#pragma unroll
-  for (int r = 0; r < 2 * R; ++r) {
-    const double v = wave_sum(agc[r]);
-    if (lane == 0) my[1 + r] = v;
-    if constexpr (OTF) {
-      const double a = wave_sum(ahm[r]);
-      const double b = wave_sum(ahg[r]);
-      if (lane == 0) {
-        my[1 + 2 * R + r] = a;
-        my[1 + 4 * R + r] = b;
-      }
-    }
+    end_half(0);
   }
 }
-
 // ---------------------------------------------------------------------------------------------
 // Normalisation as a quadratic form (fixed shapes).  In cell c the amplitude is linear in
 // v = (P_0..3 of interval j12, P_0..3 of interval j13, c_1..c_R) with the per-point functions phi of
@@ -598,8 +627,7 @@ __device__ void run_qform(const Segment& sg, const Real* tab, double* bins, doub
       gim += 4.0 * yi;
     }
   }
-  const int nsc = 1 + 2 * R;
-  double* my = scal + wave * nsc;
+  double* my = scal;  // this wave's first slot
   {
     const double v = wave_sum(acc);
     if (lane == 0) my[0] = v;
@@ -840,10 +868,12 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
   }
 }
 
+// parts: the number of consecutive parts each wave's tile range is swept in (1 with shapes floated);
+// order (0 or 1): ascending or descending part order.  The result is the same either way, bit for bit.
 template <typename Real, int R, bool OTF>
 __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, const int2* __restrict__ block_map,
                                               const Job* __restrict__ jobs, Kin<Real> kin, int max_nint,
-                                              ArgTable targ) {
+                                              ArgTable targ, int parts, int order) {
   extern __shared__ double lds[];
   const int waves = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -852,38 +882,41 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
   const Segment sg = segs[bm.x];
   const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
   const int stride = 8 * max_nint;
-  // LDS: [evaluation table | wave-private interval histograms | wave scalars]
+  // LDS: [evaluation table | interval histograms, `parts` per wave | sets of scalars, `parts` per wave]
   const int tw = (table_words(max_nint, R) * (int)sizeof(Real) + 7) / 8;
   double* tab_lds = lds;
   double* bins = lds + tw;
-  double* scal = bins + waves * stride;
+  double* scal = bins + parts * waves * stride;
   {
     const unsigned* src = sg.table ? (const unsigned*)sg.table : (const unsigned*)targ.w;
     unsigned* dst = (unsigned*)tab_lds;
     const int words = table_words(sg.nint, R) * (int)sizeof(Real) / 4;
     for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
   }
-  for (int i = threadIdx.x; i < waves * stride + waves * nsc; i += blockDim.x) bins[i] = 0.0;
+  for (int i = threadIdx.x; i < parts * waves * (stride + nsc); i += blockDim.x) bins[i] = 0.0;
   __syncthreads();
   const Real* tab = (const Real*)tab_lds;
+  double* wb = bins + parts * wave * stride;
+  double* ws = scal + parts * wave * nsc;
   if (sg.kind == 0) {
-    run_segment<Real, R, OTF, 0>(sg, kin, tab, bins + wave * stride, scal, wave, lane, waves, bm.y);
+    run_segment<Real, R, OTF, 0>(sg, kin, tab, wb, ws, wave, lane, waves, bm.y, stride, parts, order);
   } else if (sg.kind == 1) {
-    run_segment<Real, R, OTF, 1>(sg, kin, tab, bins + wave * stride, scal, wave, lane, waves, bm.y);
+    run_segment<Real, R, OTF, 1>(sg, kin, tab, wb, ws, wave, lane, waves, bm.y, stride, parts, order);
   } else {
     // the quadratic form needs the resonance amplitudes fixed: never set up with shapes floated
-    if constexpr (!OTF) run_qform<Real, R>(sg, tab, bins + wave * stride, scal, wave, lane, waves, bm.y);
+    if constexpr (!OTF) run_qform<Real, R>(sg, tab, wb, ws, wave, lane, waves, bm.y);
   }
   __syncthreads();
   const int rs = sg.rs;
   double* rec = sg.records + (long long)bm.y * rs;
   const int nb = 8 * sg.nint;
+  // waves in order, each wave's parts in order
   for (int f = threadIdx.x; f < nb + nsc; f += blockDim.x) {
     double s = 0.0;
     if (f < nb) {
-      for (int w = 0; w < waves; ++w) s += bins[w * stride + f];
+      for (int w = 0; w < parts * waves; ++w) s += bins[w * stride + f];
     } else {
-      for (int w = 0; w < waves; ++w) s += scal[w * nsc + (f - nb)];
+      for (int w = 0; w < parts * waves; ++w) s += scal[w * nsc + (f - nb)];
     }
     rec[f] = s;
   }
@@ -1240,11 +1273,19 @@ hipError_t cache_impl(int R, const Segment* s, const double* res, const Kin<doub
 
 template <typename Real, bool OTF>
 hipError_t eval_impl2(int R, const Segment* segs, const int2* bs, const Job* jobs, int nb, int waves, int max_nint,
-                      const void* kin, const ArgTable* targ, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                      const void* kin, const ArgTable* targ, int parts, int order, hipStream_t st, hipEvent_t e0,
+                      hipEvent_t e1) {
   Kin<Real> k = *(const Kin<Real>*)kin;
   const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
   const int tw = (table_words(max_nint, R) * (int)sizeof(Real) + 7) / 8;
-  const size_t lds = ((size_t)tw + (size_t)waves * (8 * max_nint + nsc)) * sizeof(double);
+  // as many parts as asked for whose histograms fit the 64 KiB a workgroup may take; one with shapes
+  // floated (that sweep is bound by the vector ALU, not by reads the Infinity Cache could serve)
+  if (OTF) parts = 1;
+  size_t lds = 0;
+  for (;; parts /= 2) {
+    lds = ((size_t)tw + (size_t)parts * waves * (8 * max_nint + nsc)) * sizeof(double);
+    if (lds <= 65536 || parts == 1) break;
+  }
   static const ArgTable empty{};
   const ArgTable* ta = targ ? targ : &empty;
   const dim3 grid(nb), block(64 * waves);
@@ -1257,7 +1298,8 @@ hipError_t eval_impl2(int R, const Segment* segs, const int2* bs, const Job* job
     case 4: fn = (const void*)k_eval<Real, 4, OTF>; break;
     default: return hipErrorInvalidValue;
   }
-  void* args[] = {(void*)&segs, (void*)&bs, (void*)&jobs, (void*)&k, (void*)&max_nint, (void*)ta};
+  void* args[] = {(void*)&segs, (void*)&bs, (void*)&jobs, (void*)&k, (void*)&max_nint, (void*)ta, (void*)&parts,
+                  (void*)&order};
   // start/stop events (when given) are recorded on the stream right before and after the dispatch
   // (events attached to the dispatch itself cost ~15 us of host time per launch on this runtime)
   if (e0) {
@@ -1295,13 +1337,16 @@ hipError_t launch_cache(bool fp64, int R, const Segment* s, const double* res64,
 }
 
 hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const int2* bs, const Job* jobs, int nb,
-                       int waves, int max_nint, const void* kin, const ArgTable* targ, hipStream_t st, hipEvent_t e0,
-                       hipEvent_t e1) {
+                       int waves, int max_nint, const void* kin, const ArgTable* targ, int parts, int order,
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   (void)hipGetLastError();
-  if (fp64) return otf ? eval_impl2<double, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1)
-                       : eval_impl2<double, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1);
-  return otf ? eval_impl2<float, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1)
-             : eval_impl2<float, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, st, e0, e1);
+  if (parts != 1 && parts != 2 && parts != 4) return hipErrorInvalidValue;
+  order &= 1;
+  if (fp64)
+    return otf ? eval_impl2<double, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, parts, order, st, e0, e1)
+               : eval_impl2<double, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, parts, order, st, e0, e1);
+  return otf ? eval_impl2<float, true>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, parts, order, st, e0, e1)
+             : eval_impl2<float, false>(R, segs, bs, jobs, nb, waves, max_nint, kin, targ, parts, order, st, e0, e1);
 }
 
 hipError_t launch_reduce(const Segment* segs, const Job* jobs, const int2* tasks, int n_tasks, int n_jobs,

@@ -83,6 +83,11 @@ mipwa_ctx::LaunchPlan mipwa_ctx::plan_launch() const {
   L.rs = record_size(mh.N - 1, mh.R, otf);
   L.G_d = n_groups(L.nb_d);
   L.G_n = n_groups(L.nb_n);
+  // bytes the sweep reads per evaluation (coordinates, cached amplitudes, normalisation weights)
+  const double real = fp64 ? 8.0 : 4.0;
+  double bytes = (double)ev.n * (2 + 2 * mh.R) * real;
+  if (!use_qform()) bytes += (double)nm.n * (3 + 2 * mh.R) * real;
+  L.parts = otf ? 1 : sweep_parts(bytes);
   return L;
 }
 
@@ -135,6 +140,7 @@ int mipwa_ctx::rebuild_launch() {
   nb_n = L.nb_n;
   n_blocks = L.B;
   rs = L.rs;
+  sweep_parts_eff = L.parts;
   const bool qf = use_qform();
   HIPCHK(d_records.alloc((size_t)L.B * L.rs * sizeof(double)), "records allocation");
   HIPCHK(d_grec.alloc((size_t)(L.G_d + L.G_n) * L.rs * sizeof(double)), "group records allocation");
@@ -257,13 +263,15 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigne
   // with use_arg the table and theta travel in the kernel arguments (copied at the launch)
   HIPCHK(launch_eval(fp64, mh.R, otf, d_segs.as<Segment>(), d_block_seg.as<int2>(), d_job.as<Job>() + (to_host ? 0 : 1),
                      n_blocks, waves_eff, mh.N - 1, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32,
-                     use_arg ? &h_args : nullptr, st, timed ? ev_t[cs][1] : nullptr, timed ? ev_t[cs][2] : nullptr),
+                     use_arg ? &h_args : nullptr, sweep_parts_eff, sweep_order, st, timed ? ev_t[cs][1] : nullptr,
+                     timed ? ev_t[cs][2] : nullptr),
          "likelihood kernel");
   HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), d_tasks.as<int2>(), n_tasks, 1,
                        use_arg ? &h_args : nullptr, st, s, out, &h_jobs[to_host ? 0 : 1]),
          "reduction kernels");
   HIPCHK(hipEventRecord(ev_done, st), "event");
   last_st = st;
+  sweep_order ^= 1;
   if (timed) {
     HIPCHK(hipEventRecord(ev_t[cs][3], st), "event");
     ev_last = cs;

@@ -162,10 +162,12 @@ extern "C" int mipwa_eval_noalloc(mipwa_ctx* ctx, void* stream, double* d_out) {
   }
   const ArgTable* args = ctx->use_arg ? &ctx->h_args : nullptr;
   NACHK(launch_eval(ctx->fp64, ctx->mh.R, ctx->otf, d_seg, d_bmap, d_job, L.B, L.waves, ctx->mh.N - 1,
-                    ctx->fp64 ? (const void*)&ctx->mh.kin64 : (const void*)&ctx->mh.kin32, args, st),
+                    ctx->fp64 ? (const void*)&ctx->mh.kin64 : (const void*)&ctx->mh.kin32, args, L.parts, ctx->sweep_order,
+                    st),
         "likelihood kernel");
   NACHK(launch_reduce(d_seg, d_job, d_tasks, T, 1, args, st, 0, d_out, &a.job), "reduction kernels");
   NACHK(hipEventRecord(ctx->ev_done, st), "event");
   ctx->last_st = st;
+  ctx->sweep_order ^= 1;
   return MIPWA_OK;
 }

@@ -157,6 +157,7 @@ struct mipwa_server {
   bool fp64 = false;
   size_t budget = 0;
   hipStream_t stream = nullptr;
+  int sweep_order = 0;  // ascending or descending order of each wave's parts of tiles; alternates per step
   std::mutex mu;       // all job and queue state
   std::mutex norm_mu;  // creation of shared normalisation sets
   std::condition_variable cv_sched, cv_done;
@@ -550,14 +551,19 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
     if (launch_upload(db, S->h_batch.dev, off, S->stream) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batch upload failed");
     const ModelHost& mh0 = js[0]->mh;
+    double step_bytes = 0.0;  // event streams of the step (the normalisation enters as per-cell moments)
+    for (int j = 0; j < nj; ++j) step_bytes += (double)js[j]->ev.n * (2 + 2 * R) * (S->fp64 ? 8.0 : 4.0);
     if (launch_eval(S->fp64, R, false, reinterpret_cast<const Segment*>(db + o_seg),
                     reinterpret_cast<const int2*>(db + o_map), reinterpret_cast<const Job*>(db + o_job),
                     (int)map.size(), kServeWaves, max_nint,
-                    S->fp64 ? (const void*)&mh0.kin64 : (const void*)&mh0.kin32, nullptr, S->stream) != hipSuccess)
+                    S->fp64 ? (const void*)&mh0.kin64 : (const void*)&mh0.kin32, nullptr, sweep_parts(step_bytes),
+                    S->sweep_order,
+                    S->stream) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batched likelihood kernel failed");
     if (launch_reduce(reinterpret_cast<const Segment*>(db + o_seg), reinterpret_cast<const Job*>(db + o_job),
                       reinterpret_cast<const int2*>(db + o_task), (int)tasks.size(), nj, nullptr, S->stream) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batched reduction kernels failed");
+    S->sweep_order ^= 1;
     const auto t_l = Clock::now();
     // spin on the stream (the scheduler has nothing else to do meanwhile): a blocking wait wakes up
     // late while the host is busy with the jobs' threads

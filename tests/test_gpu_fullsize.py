@@ -1,10 +1,10 @@
 """Checks at the benchmark workloads' full sizes, in the launch configuration bench.py times.
 
 The oracle computes -2 ln L and the knot and coefficient gradient at 10M + 10M points and at 1M + 2M
-points; at 5M + 5M with masses and widths floated (where the oracle's per-point five-point
-differences would take minutes) the checks are properties that hold at any size: the FP64 adjoint
-against central differences of the library's FP64 -2 ln L, and the mixed-precision gradient against
-the FP64 one.
+points, and at 5M + 5M with masses and widths floated the whole gradient including the mass and width
+partials (its per-point five-point differences split over the host's cores by oracle.pool); there the
+FP64 adjoint is also checked against central differences of the library's FP64 -2 ln L, and the
+mixed-precision gradient against the FP64 one.
 """
 import numpy as np
 import pytest
@@ -86,6 +86,7 @@ def test_fp64_gradient_full_size_1m():
 
 
 def test_shape_gradient_full_size_5m():
+    from oracle.pool import OraclePool
     from paper_1703_03284_amd import context_for
     wl = synth.C4
     d = wl.decay
@@ -94,6 +95,8 @@ def test_shape_gradient_full_size_5m():
     s12, s13 = synth.uniform_phase_space(d, wl.n_norm, wl.seed("norm"))
     w = np.full(len(s12), K.area(m) / len(s12))
     th = wl.start()
+    with OraclePool(m, ev, (s12, s13, w)) as pool:
+        v_o, g_o = pool.nll_and_grad(th, shapes=True)
     ctxs = {}
     for prec in ("fp64", "mixed"):
         c = context_for(d, wl.knots(), wl.resonances, _prec(prec))
@@ -103,6 +106,13 @@ def test_shape_gradient_full_size_5m():
         ctxs[prec] = c
     v64, g64 = ctxs["fp64"].eval(th)
     v32, g32 = ctxs["mixed"].eval(th)
+    # against the oracle: every parameter, the mass and width partials included (the oracle's come from
+    # five-point differences of the amplitudes, so the FP64 bound is that of the parity tests with
+    # shapes floated)
+    assert rel(v64, v_o) <= 1e-10, (v64, v_o)
+    assert rel(v32, v_o) <= 1e-6, (v32, v_o)
+    assert np.abs(g64 - g_o).max() <= 1e-7 * np.abs(g_o).max(), np.abs(g64 - g_o).max() / np.abs(g_o).max()
+    assert np.abs(g32 - g_o).max() <= 1e-4 * np.abs(g_o).max(), np.abs(g32 - g_o).max() / np.abs(g_o).max()
     assert rel(v32, v64) <= 1e-6
     assert np.abs(g32 - g64).max() <= 1e-4 * np.abs(g64).max()
     N, R = wl.n_knots, wl.n_res
