@@ -232,23 +232,28 @@ int mipwa_density_max(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t
 int mipwa_toy(mipwa_ctx* ctx, const double* theta, int n_theta, uint64_t seed, int64_t n_probe, int64_t n,
               double* s12_out, double* s13_out, double* fmax_out);
 
-/* Device time of the most recent evaluation's kernels in milliseconds (HIP events around the resonance
- * cache build, the streaming likelihood kernel and the reduction); *stream_ms is the streaming kernel
- * alone.  Nullable outputs. */
+/* Device times of the most recent timed evaluations (see mipwa_set_timing), in milliseconds: *total_ms
+ * from before the first launch to the end of the finish, *stream_ms of the streaming likelihood kernel
+ * alone; a figure that the last two timed evaluations did not record is NaN.  Nullable outputs.
+ * Errors: E_STATE (nothing timed yet). */
 int mipwa_last_timing(const mipwa_ctx* ctx, double* total_ms, double* stream_ms);
 
-/* Accumulate device timings of every synchronous evaluation (on = 1) from HIP events recorded on the
- * evaluation's stream; resets the statistics.  mipwa_timing_stats returns the number of timed
- * evaluations and the mean device time of the whole evaluation (upload to finish) and of the
- * streaming kernel alone, in milliseconds. */
-int mipwa_set_timing(mipwa_ctx* ctx, int on);
+/* Device timing from HIP events recorded on the evaluation's stream (synchronous and asynchronous
+ * evaluations).  period 0 turns it off; period n >= 1 times every n-th evaluation, and the timed
+ * evaluations alternately record the whole evaluation (before the first launch to after the finish)
+ * and the streaming kernel alone: each recorded event adds device time to its evaluation (a few
+ * microseconds), so a sample every few evaluations leaves the rate of the others as it is.  Resets
+ * the statistics.  mipwa_timing_stats returns the number of timed evaluations, the mean time of the
+ * whole evaluation and the mean time of the streaming kernel over the evaluations that recorded each,
+ * in milliseconds (NaN when none did).  Errors: E_INVAL (period < 0). */
+int mipwa_set_timing(mipwa_ctx* ctx, int period);
+int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_ms, double* mean_stream_ms);
 
 /* Measured streaming-read ceiling of a GPU, the denominator beside the datasheet peak when the
  * likelihood sweep's bandwidth is reported: a buffer of `bytes` (>= 1 MiB) is read with 16-byte
  * non-temporal loads and no other work, `reps` times after one warm-up; *gbs receives the best rate in
  * GB/s.  Allocates and frees its own buffer.  Errors: E_INVAL, E_NOMEM, E_HIP. */
 int mipwa_read_bandwidth(int device, int64_t bytes, int reps, double* gbs);
-int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_ms, double* mean_stream_ms);
 
 /* Launch shape of the streaming kernel: blocks (0 = default) and waves per block (0 = default, 1..16).
  * Takes effect at the next load.  Errors: E_INVAL. */

@@ -182,17 +182,19 @@ class Context:
                     "eval_noalloc")
 
     def timing(self):
-        """(device ms of cache+stream+reduce, device ms of the streaming kernel) of the last evaluation."""
+        """(device ms of the whole evaluation, device ms of the streaming kernel) of the last timed
+        evaluations (NaN for a figure they did not record; see set_timing)."""
         a, b = C.c_double(), C.c_double()
         self._check(self._lib.mipwa_last_timing(self._h, C.byref(a), C.byref(b)), "last_timing")
         return a.value, b.value
 
-    def set_timing(self, on=True):
-        """Accumulate device timings (HIP events on the evaluation stream) of every synchronous eval."""
-        self._check(self._lib.mipwa_set_timing(self._h, int(bool(on))), "set_timing")
+    def set_timing(self, period=1):
+        """Device timing from HIP events on the evaluation stream of every period-th evaluation (0: off);
+        timed evaluations alternately record the whole evaluation and the streaming kernel."""
+        self._check(self._lib.mipwa_set_timing(self._h, int(period)), "set_timing")
 
     def timing_stats(self):
-        """(count, mean device ms of the whole evaluation, mean ms of the streaming kernel)."""
+        """(timed evaluations, mean device ms of the whole evaluation, mean ms of the streaming kernel)."""
         n, a, b = C.c_longlong(), C.c_double(), C.c_double()
         self._check(self._lib.mipwa_timing_stats(self._h, C.byref(n), C.byref(a), C.byref(b)), "timing_stats")
         return n.value, a.value, b.value

@@ -49,8 +49,11 @@ struct mipwa_ctx {
   int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0, n_tasks = 0;
   bool launch_dirty = true;
 
-  // Timing events: two sets [before the sweep, sweep start, sweep end, after the finish] used in
-  // turn, so that an evaluation reads the previous one's times after its own launches are queued.
+  // Timing events: two sets [before the first launch, sweep start, sweep end, after the finish] used
+  // in turn, so that an evaluation reads the previous one's times after its own launches are queued.
+  // A timed evaluation records one pair only: the step pair (first and last) or the sweep pair
+  // (second and third), alternately; each pair costs device time, so timing samples every
+  // timing_period-th evaluation.
   hipEvent_t ev_staged = nullptr;
   // Completion of the last enqueued evaluation and the stream it went to.  The context's scratch
   // (records, group records, tables, resonance cache, moments) is shared by every stream an
@@ -66,10 +69,13 @@ struct mipwa_ctx {
   int ev_cur = 0;                 // set the next timed evaluation records into
   int ev_last = 0;                // set of the last timed evaluation
   bool set_unread[2] = {false, false};
+  int set_kind[2] = {0, 0};       // 0: the step pair was recorded in the set, 1: the sweep pair
   bool timing_pending = false;
-  bool timing_on = false;
+  int timing_period = 0;          // 0: off; n: every n-th evaluation is timed
+  unsigned long long timing_calls = 0;
+  int timing_next_kind = 0;
+  long long t_count_step = 0, t_count_sweep = 0;
   unsigned long long seq = 0;     // sequence number of the last synchronous evaluation
-  long long t_count = 0;
   double t_total = 0.0, t_stream = 0.0;
 
 
@@ -110,6 +116,7 @@ struct mipwa_ctx {
   int enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigned long long s = 0, double* out = nullptr);
   size_t upload16() const { return (upload_bytes + 15) / 16 * 16; }
   int wait_result(unsigned long long s);
+  bool take_timing() { return timing_period > 0 && timing_calls++ % (unsigned long long)timing_period == 0; }
   int fold_timing(int set);
   int fold_all_timing();
   int run_sync_eval();

@@ -255,7 +255,8 @@ int mipwa_ctx::drain() {
 int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigned long long s, double* out) {
   mipwa_ctx* ctx = this;
   const int cs = ev_cur;
-  if (timed) HIPCHK(hipEventRecord(ev_t[cs][0], st), "event");
+  const int kind = timed ? timing_next_kind : -1;  // 0: step pair, 1: sweep pair
+  if (kind == 0) HIPCHK(hipEventRecord(ev_t[cs][0], st), "event");
   if (!use_arg) {
     HIPCHK(launch_upload(d_blob.p, h_blob.dev, upload16(), st), "parameter upload");
     HIPCHK(hipEventRecord(ev_staged, st), "event");
@@ -263,8 +264,8 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigne
   // with use_arg the table and theta travel in the kernel arguments (copied at the launch)
   HIPCHK(launch_eval(fp64, mh.R, otf, d_segs.as<Segment>(), d_block_seg.as<int2>(), d_job.as<Job>() + (to_host ? 0 : 1),
                      n_blocks, waves_eff, mh.N - 1, fp64 ? (const void*)&mh.kin64 : (const void*)&mh.kin32,
-                     use_arg ? &h_args : nullptr, sweep_parts_eff, sweep_order, st, timed ? ev_t[cs][1] : nullptr,
-                     timed ? ev_t[cs][2] : nullptr),
+                     use_arg ? &h_args : nullptr, sweep_parts_eff, sweep_order, st, kind == 1 ? ev_t[cs][1] : nullptr,
+                     kind == 1 ? ev_t[cs][2] : nullptr),
          "likelihood kernel");
   HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), d_tasks.as<int2>(), n_tasks, 1,
                        use_arg ? &h_args : nullptr, st, s, out, &h_jobs[to_host ? 0 : 1]),
@@ -273,7 +274,11 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigne
   last_st = st;
   sweep_order ^= 1;
   if (timed) {
-    HIPCHK(hipEventRecord(ev_t[cs][3], st), "event");
+    if (kind == 0) HIPCHK(hipEventRecord(ev_t[cs][3], st), "event");
+    set_kind[cs] = kind;
+    timing_next_kind ^= 1;
+    set_unread[cs] = true;
+    timing_pending = true;
     ev_last = cs;
     ev_cur = cs ^ 1;
     // the other set holds the previous timed evaluation: take its times now that this one is queued
@@ -330,13 +335,18 @@ int mipwa_ctx::fold_timing(int set) {
   mipwa_ctx* ctx = this;
   if (!set_unread[set]) return MIPWA_OK;
   set_unread[set] = false;
-  HIPCHK(hipEventSynchronize(ev_t[set][3]), "event sync");
-  float a = 0, b = 0;
-  if (hipEventElapsedTime(&a, ev_t[set][0], ev_t[set][3]) == hipSuccess &&
-      hipEventElapsedTime(&b, ev_t[set][1], ev_t[set][2]) == hipSuccess) {
-    t_count += 1;
-    t_total += a;
-    t_stream += b;
+  const bool step = set_kind[set] == 0;
+  hipEvent_t e0 = step ? ev_t[set][0] : ev_t[set][1], e1 = step ? ev_t[set][3] : ev_t[set][2];
+  HIPCHK(hipEventSynchronize(e1), "event sync");
+  float a = 0;
+  if (hipEventElapsedTime(&a, e0, e1) == hipSuccess) {
+    if (step) {
+      t_count_step += 1;
+      t_total += a;
+    } else {
+      t_count_sweep += 1;
+      t_stream += a;
+    }
   }
   (void)hipGetLastError();
   return MIPWA_OK;
@@ -354,12 +364,9 @@ int mipwa_ctx::run_sync_eval() {
   // numbers are unique in the process: pinned memory handed back by a destroyed context may still
   // hold one of its sequence numbers
   const unsigned long long s = seq = g_eval_seq.fetch_add(1, std::memory_order_relaxed) + 1;
-  rc = enqueue_kernels(stream, true, timing_on, s);
+  rc = enqueue_kernels(stream, true, take_timing(), s);
   if (rc) return rc;
-  rc = wait_result(s);
-  if (rc) return rc;
-  if (timing_on) set_unread[ev_last] = timing_pending = true;
-  return MIPWA_OK;
+  return wait_result(s);
 }
 
 // ---- C ABI -----------------------------------------------------------------------------------
@@ -585,31 +592,41 @@ int mipwa_eval_async(mipwa_ctx* ctx, void* stream, double* d_out) {
   hipStream_t st = (hipStream_t)stream;
   int rc = ctx->prepare_eval(st);
   if (rc) return rc;
-  rc = ctx->enqueue_kernels(st, false, true, 0, d_out);
-  if (rc) return rc;
-  ctx->timing_pending = true;
-  return MIPWA_OK;
+  return ctx->enqueue_kernels(st, false, ctx->take_timing(), 0, d_out);
 }
 
 int mipwa_last_timing(const mipwa_ctx* cctx, double* total_ms, double* stream_ms) {
   mipwa_ctx* ctx = const_cast<mipwa_ctx*>(cctx);
   if (!ctx) return MIPWA_E_INVAL;
   if (!ctx->timing_pending) return ctx->fail(MIPWA_E_STATE, "no evaluation timed yet");
-  const int set = ctx->ev_last;
-  HIPCHK(hipEventSynchronize(ctx->ev_t[set][3]), "event sync");
-  float a = 0, b = 0;
-  HIPCHK(hipEventElapsedTime(&a, ctx->ev_t[set][0], ctx->ev_t[set][3]), "event time");
-  HIPCHK(hipEventElapsedTime(&b, ctx->ev_t[set][1], ctx->ev_t[set][2]), "event time");
-  if (total_ms) *total_ms = a;
-  if (stream_ms) *stream_ms = b;
+  // the two sets hold the last two timed evaluations, one of each pair when both exist
+  double v[2] = {NAN, NAN};
+  for (int k = 0; k < 2; ++k) {
+    const int set = ctx->ev_last ^ k;
+    if (k == 1 && ctx->set_kind[set] == ctx->set_kind[ctx->ev_last]) break;
+    const bool step = ctx->set_kind[set] == 0;
+    hipEvent_t e0 = step ? ctx->ev_t[set][0] : ctx->ev_t[set][1], e1 = step ? ctx->ev_t[set][3] : ctx->ev_t[set][2];
+    float a = 0;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&a, e0, e1) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    v[step ? 0 : 1] = a;
+  }
+  if (total_ms) *total_ms = v[0];
+  if (stream_ms) *stream_ms = v[1];
   return MIPWA_OK;
 }
 
-int mipwa_set_timing(mipwa_ctx* ctx, int on) {
+int mipwa_set_timing(mipwa_ctx* ctx, int period) {
   if (!ctx) return MIPWA_E_INVAL;
-  ctx->timing_on = on != 0;
+  if (period < 0) return ctx->fail(MIPWA_E_INVAL, "the timing period must be >= 0");
+  if (int rc = ctx->fold_all_timing()) return rc;  // finish with the events still in use
+  ctx->timing_period = period;
+  ctx->timing_calls = 0;
+  ctx->timing_next_kind = 0;
   ctx->set_unread[0] = ctx->set_unread[1] = false;
-  ctx->t_count = 0;
+  ctx->t_count_step = ctx->t_count_sweep = 0;
   ctx->t_total = ctx->t_stream = 0.0;
   return MIPWA_OK;
 }
@@ -617,10 +634,9 @@ int mipwa_set_timing(mipwa_ctx* ctx, int on) {
 int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_ms, double* mean_stream_ms) {
   if (!ctx) return MIPWA_E_INVAL;
   if (int rc = const_cast<mipwa_ctx*>(ctx)->fold_all_timing()) return rc;
-  const double n = ctx->t_count > 0 ? (double)ctx->t_count : 1.0;
-  if (count) *count = ctx->t_count;
-  if (mean_total_ms) *mean_total_ms = ctx->t_total / n;
-  if (mean_stream_ms) *mean_stream_ms = ctx->t_stream / n;
+  if (count) *count = ctx->t_count_step + ctx->t_count_sweep;
+  if (mean_total_ms) *mean_total_ms = ctx->t_count_step ? ctx->t_total / ctx->t_count_step : NAN;
+  if (mean_stream_ms) *mean_stream_ms = ctx->t_count_sweep ? ctx->t_stream / ctx->t_count_sweep : NAN;
   return MIPWA_OK;
 }
 
