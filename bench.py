@@ -296,6 +296,9 @@ def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
             "capacity_fits_per_s": capacity, "arrival_rate_per_s": rate,
             "fits_per_s": st1["fits_per_s"], "p50_s": st1["p50_s"], "p99_s": st1["p99_s"],
             "mean_batch": st1["mean_batch"], "steps": st1["steps"], "peak_bytes": st1["peak_bytes"],
+            "capacity_device_busy": st0["device_busy"], "capacity_step_device_us": 1e6 * st0["step_device_s"],
+            "capacity_mean_batch": st0["mean_batch"], "capacity_steps": st0["steps"],
+            "device_busy": st1["device_busy"], "step_device_us": 1e6 * st1["step_device_s"],
             "converged": ok1[0], "not_converged": ok1[1], "tol_edm": 1e-4,
             "mean_evals_per_fit": float(np.mean([r.get("n_eval", 0) for r in res1])),
             "precision": "mixed" if precision == 1 else "fp64"}

@@ -264,9 +264,12 @@ int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves_per_block);
  * Dalitz-plot PDF) against one shared normalisation sample.  Jobs wait until their device footprint
  * fits the HBM budget, then load (cell sort and resonance cache on their own stream) and run the BFGS
  * fit of mipwa_fit in a worker thread.  Every evaluation a job needs is batched with the pending
- * evaluations of all other active jobs into a single launch of the streaming kernel; a step starts
- * once every active job has asked, or 100 us after the first request, and jobs admitted while a step
- * runs join the next one.  A job's result does not depend on which other jobs share its steps (its
+ * evaluations of other active jobs into a single launch of the streaming kernel.  Up to two steps are
+ * in flight: while one runs, the next is formed from the jobs outside it and queued behind it, so the
+ * jobs' host work overlaps the device's (a step formed with none in flight takes at most half of the
+ * active jobs, which splits them into two groups that alternate).  A step is launched once every
+ * active job outside the steps in flight has asked, or 50 us after its first request; jobs admitted
+ * while a step runs join a later one.  A job's result does not depend on which other jobs share its steps (its
  * kernel blocks and reduction order depend only on its own sizes).  Serving jobs keep masses and
  * widths fixed.  The server is thread-safe.  With MIPWA_SERVE_TRACE set in the environment, admission,
  * loading, completion and the scheduler's time split are printed to stderr. */
@@ -278,6 +281,8 @@ typedef struct {
   int64_t peak_bytes;  /* largest admitted device footprint (events, scratch, normalisation sets) */
   int64_t steps;       /* batched launches so far */
   double mean_batch;   /* mean number of jobs per launch */
+  double step_device_s; /* mean device time of a step (HIP events around every 16th step's kernels) */
+  double device_busy;  /* step_device_s x steps / (last completion - first submission) */
 } mipwa_serve_stats;
 
 /* Create a server on `device` in `precision`; hbm_budget_bytes = 0 uses 80% of the free memory.

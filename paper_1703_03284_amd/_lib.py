@@ -34,7 +34,8 @@ class FitInfoC(C.Structure):
 class ServeStatsC(C.Structure):
     _fields_ = [("fits_per_s", C.c_double), ("p50_s", C.c_double), ("p99_s", C.c_double),
                 ("n_done", C.c_longlong), ("n_active", C.c_longlong), ("n_queued", C.c_longlong),
-                ("peak_bytes", C.c_longlong), ("steps", C.c_longlong), ("mean_batch", C.c_double)]
+                ("peak_bytes", C.c_longlong), ("steps", C.c_longlong), ("mean_batch", C.c_double),
+                ("step_device_s", C.c_double), ("device_busy", C.c_double)]
 
 
 _P = C.c_void_p

@@ -45,9 +45,15 @@ namespace {
 constexpr int kServeWaves = 4;
 constexpr int kServeTilesPerWave = 8;
 constexpr int kMaxSegBlocks = 512;
-constexpr int kBatchWindowUs = 100;
+constexpr int kBatchWindowUs = 50;
+constexpr int kStepTimingPeriod = 16;
 constexpr size_t kBatchBytes0 = (size_t)4 << 20;   // initial step descriptor buffer (host and device)
 constexpr size_t kResultBytes0 = (size_t)1 << 20;  // initial result buffer (mapped host memory)
+constexpr size_t kSeqBytes0 = (size_t)64 << 10;    // initial sequence words: 8192 jobs per step
+
+// Sequence numbers of serving steps, unique in the process: pinned memory handed back by a destroyed
+// server may still hold one of its numbers.
+std::atomic<unsigned long long> g_step_seq{0};
 
 // blocks of a job's event segment: about kServeTilesPerWave tiles per wave
 int seg_blocks(int n_tiles) {
@@ -157,7 +163,9 @@ struct mipwa_server {
   bool fp64 = false;
   size_t budget = 0;
   hipStream_t stream = nullptr;
-  int sweep_order = 0;  // ascending or descending order of each wave's parts of tiles; alternates per step
+  // Serving sweeps every job in one part (launch_eval): the part count changes the rounding of a
+  // job's sums, and a job's result must not depend on the other jobs of its steps.
+  int sweep_order = 0;
   std::mutex mu;       // all job and queue state
   std::mutex norm_mu;  // creation of shared normalisation sets
   std::condition_variable cv_sched, cv_done;
@@ -172,17 +180,34 @@ struct mipwa_server {
   int running = 0;  // LOADING + ACTIVE
   int n_active = 0;  // ACTIVE: jobs that ask for evaluations
   int n_req = 0;     // ACTIVE jobs with a request not yet taken into a batch
+  int n_inflight = 0;  // jobs whose evaluation is in a step in flight
   long long steps = 0;
   double batch_sum = 0;
   // scheduler time (s): idle until a request, in the batching window, staging the step, on the GPU
   // and handing results back to the jobs' threads, admitting jobs and joining finished ones
   double t_idle = 0, t_window = 0, t_stage = 0, t_gpu = 0, t_wake = 0, t_admit = 0;
+  long long n_overlapped = 0;  // steps launched while the previous step was still in flight
   bool any_submit = false;
   Clock::time_point t_first_submit, t_last_done, t_create = Clock::now();
   std::vector<double> latencies;
-  HostBuf h_batch, h_res;
-  DevBuf d_batch;
-  double* h_res_dev = nullptr;
+  // Buffers of a step: descriptors (pinned host memory, copied to the device by the step's first
+  // kernel), results and one sequence word per job (mapped host memory: the finish stores the step's
+  // sequence number after a job's results, and the scheduler polls it).  Two sets, used by
+  // alternate steps, so that a step can be formed while the previous one runs.
+  struct StepBufs {
+    HostBuf h_batch, h_res, h_seq;
+    DevBuf d_batch;
+    double* h_res_dev = nullptr;
+    unsigned long long* h_seq_dev = nullptr;
+  } bufs[2];
+  int next_buf = 0;
+  // device time of every kStepTimingPeriod-th step (a pair of events around its kernels); the events
+  // and the figures below are guarded by timing_mu (the scheduler records, mipwa_server_stats reads)
+  std::mutex timing_mu;
+  hipEvent_t ev_step[2] = {nullptr, nullptr};
+  bool step_timed_unread = false;
+  long long n_step_timed = 0;
+  double step_dev_ms = 0.0;
   std::string err;
 
   // err is written by the callers' threads and by the scheduler: under its own lock
@@ -393,12 +418,13 @@ static void serve_worker(mipwa_server* S, SJob* J) {
       J->done = false;
     }
     {
-      // the scheduler is woken by the first request of a step and by the one that completes it
+      // the scheduler is woken by the first request of a step and by the one that completes it (every
+      // active job outside the steps in flight has asked)
       std::lock_guard<std::mutex> lk(S->mu);
       if (S->stop) return MIPWA_E_CANCELLED;
       J->req = true;
       S->n_req += 1;
-      if (S->n_req == 1 || S->n_req >= S->n_active) S->cv_sched.notify_one();
+      if (S->n_req == 1 || S->n_req >= S->n_active - S->n_inflight) S->cv_sched.notify_one();
     }
     std::unique_lock<std::mutex> jl(J->m);
     J->cv.wait(jl, [&] { return J->done || J->cancel || S->stop; });
@@ -434,79 +460,111 @@ static void serve_worker(mipwa_server* S, SJob* J) {
 
 namespace {
 
-// One batched step: every job in `batch` (same resonance count) evaluated in one launch.
-int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
-  std::map<int, std::vector<SJob*>> by_r;
-  for (SJob* J : batch) by_r[J->mh.R].push_back(J);
-  // results (mapped host memory) for every job of the step
+// A batched step: the jobs it carries (every pending evaluation of one or more resonance counts, one
+// launch per count), where their results and sequence words are, and the sequence number their
+// finish publishes.
+struct Step {
+  std::vector<SJob*> batch;
+  std::vector<size_t> res_off;  // per job: offset of its results in the step's result buffer
+  unsigned long long seq = 0;
+  int buf = 0;
+  bool timed = false;
+};
+
+// Stage and launch one step on the server's stream; returns without waiting for it.  The step's buffer
+// set is not in use: the step that last used it has been waited on.
+int launch_step(mipwa_server* S, Step& st) {
+  mipwa_server::StepBufs& B = S->bufs[st.buf];
+  std::vector<SJob*>& batch = st.batch;
+  std::map<int, std::vector<int>> by_r;  // resonance count -> positions in batch
+  for (int i = 0; i < (int)batch.size(); ++i) by_r[batch[i]->mh.R].push_back(i);
   size_t res_total = 0;
-  std::map<SJob*, size_t> res_of;
-  for (SJob* J : batch) {
-    res_of[J] = res_total;
-    res_total += 1 + J->mh.P;
+  st.res_off.resize(batch.size());
+  for (size_t i = 0; i < batch.size(); ++i) {
+    st.res_off[i] = res_total;
+    res_total += 1 + batch[i]->mh.P;
   }
-  if (S->h_res.bytes < res_total * 8) {
-    if (S->h_res.alloc(res_total * 8 * 2, true) != hipSuccess ||
-        hipHostGetDevicePointer((void**)&S->h_res_dev, S->h_res.p, 0) != hipSuccess)
+  // (larger than the initial buffers only for steps of thousands of jobs)
+  if (B.h_res.bytes < res_total * 8) {
+    if (B.h_res.alloc(res_total * 8 * 2, true) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&B.h_res_dev, B.h_res.p, 0) != hipSuccess)
       return S->fail(MIPWA_E_NOMEM, "result buffer allocation failed");
   }
+  if (B.h_seq.bytes < batch.size() * 8) {
+    if (B.h_seq.alloc(batch.size() * 8 * 2, true) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&B.h_seq_dev, B.h_seq.p, 0) != hipSuccess)
+      return S->fail(MIPWA_E_NOMEM, "sequence buffer allocation failed");
+    std::memset(B.h_seq.p, 0, B.h_seq.bytes);
+  }
+  st.seq = g_step_seq.fetch_add(1, std::memory_order_relaxed) + 1;
+  // Layout of the step's upload: per resonance count a block map, tasks, segments, jobs and the jobs'
+  // tables.  All of it is laid out first, so that the buffers are grown (if at all) before any launch.
+  struct Group {
+    int R = 0, nj = 0, max_nint = 1;
+    std::vector<int> jobs;  // positions in batch
+    std::vector<int2> map, tasks;
+    size_t o_map = 0, o_task = 0, o_seg = 0, o_job = 0;
+    std::vector<size_t> o_tab, o_th;
+  };
+  std::vector<Group> groups;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return o;
+  };
   for (auto& kv : by_r) {
-    const int R = kv.first;
-    std::vector<SJob*>& js = kv.second;
-    const int nj = (int)js.size();
+    Group g;
+    g.R = kv.first;
+    g.jobs = kv.second;
+    g.nj = (int)g.jobs.size();
+    auto J = [&](int j) { return batch[g.jobs[j]]; };
     // block map: data segments job-major, then normalisation segments interleaved by block index
     // among the jobs sharing a normalisation set
-    std::vector<int2> map;
-    for (int j = 0; j < nj; ++j)
-      for (int b = 0; b < js[j]->nb_d; ++b) map.push_back(int2{2 * j, b});
+    for (int j = 0; j < g.nj; ++j)
+      for (int b = 0; b < J(j)->nb_d; ++b) g.map.push_back(int2{2 * j, b});
     std::map<NormSet*, std::vector<int>> by_norm;
-    for (int j = 0; j < nj; ++j) by_norm[js[j]->norm].push_back(j);
+    for (int j = 0; j < g.nj; ++j) by_norm[J(j)->norm].push_back(j);
     for (auto& nk : by_norm)
-      for (int b = 0; b < js[nk.second[0]]->nb_q; ++b)
-        for (int j : nk.second) map.push_back(int2{2 * j + 1, b});
-    // layout of the step's upload
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-      const size_t o = off;
-      off = (off + bytes + 255) / 256 * 256;
-      return o;
-    };
-    std::vector<int2> tasks;
-    for (int j = 0; j < nj; ++j) {
-      for (int g = 0; g < js[j]->G_d; ++g) tasks.push_back(int2{2 * j, g});
-      for (int g = 0; g < js[j]->G_n; ++g) tasks.push_back(int2{2 * j + 1, g});
+      for (int b = 0; b < J(nk.second[0])->nb_q; ++b)
+        for (int j : nk.second) g.map.push_back(int2{2 * j + 1, b});
+    for (int j = 0; j < g.nj; ++j) {
+      for (int q = 0; q < J(j)->G_d; ++q) g.tasks.push_back(int2{2 * j, q});
+      for (int q = 0; q < J(j)->G_n; ++q) g.tasks.push_back(int2{2 * j + 1, q});
     }
-    const size_t o_map = take(map.size() * sizeof(int2));
-    const size_t o_task = take(tasks.size() * sizeof(int2));
-    const size_t o_seg = take((size_t)2 * nj * sizeof(Segment));
-    const size_t o_job = take((size_t)nj * sizeof(Job));
-    std::vector<size_t> o_tab(nj), o_th(nj);
-    int max_nint = 1;
-    for (int j = 0; j < nj; ++j) {
+    g.o_map = take(g.map.size() * sizeof(int2));
+    g.o_task = take(g.tasks.size() * sizeof(int2));
+    g.o_seg = take((size_t)2 * g.nj * sizeof(Segment));
+    g.o_job = take((size_t)g.nj * sizeof(Job));
+    g.o_tab.resize(g.nj);
+    g.o_th.resize(g.nj);
+    for (int j = 0; j < g.nj; ++j) {
       size_t toff = 0;
-      const size_t bytes = staged_bytes(js[j]->mh, S->fp64, &toff);
-      o_tab[j] = take(bytes);
-      o_th[j] = o_tab[j] + toff;
-      max_nint = std::max(max_nint, js[j]->mh.N - 1);
+      g.o_tab[j] = take(staged_bytes(J(j)->mh, S->fp64, &toff));
+      g.o_th[j] = g.o_tab[j] + toff;
+      g.max_nint = std::max(g.max_nint, J(j)->mh.N - 1);
     }
-    // grown geometrically: batches grow step by step while jobs become active, and each
-    // reallocation of pinned or device memory costs milliseconds (a device free synchronises)
-    if (off > S->h_batch.bytes || off > S->d_batch.bytes) {
-      const size_t cap = std::max(off, 2 * std::max(S->h_batch.bytes, S->d_batch.bytes));
-      if (S->h_batch.alloc(cap, true) != hipSuccess || S->d_batch.alloc(cap) != hipSuccess)
-        return S->fail(MIPWA_E_NOMEM, "batch buffer allocation failed");
-    }
-    char* hb = S->h_batch.as<char>();
-    char* db = S->d_batch.as<char>();
-    std::memcpy(hb + o_map, map.data(), map.size() * sizeof(int2));
-    std::memcpy(hb + o_task, tasks.data(), tasks.size() * sizeof(int2));
-    Segment* sg = reinterpret_cast<Segment*>(hb + o_seg);
-    Job* jb = reinterpret_cast<Job*>(hb + o_job);
-    std::memset(sg, 0, (size_t)2 * nj * sizeof(Segment));
-    std::memset(jb, 0, (size_t)nj * sizeof(Job));
-    for (int j = 0; j < nj; ++j) {
-      SJob* J = js[j];
-      std::memcpy(hb + o_tab[j], J->staged.data(), J->staged.size());
+    groups.push_back(std::move(g));
+  }
+  // grown geometrically: batches grow step by step while jobs become active, and each
+  // reallocation of pinned or device memory costs milliseconds (a device free synchronises)
+  if (off > B.h_batch.bytes || off > B.d_batch.bytes) {
+    const size_t cap = std::max(off, 2 * std::max(B.h_batch.bytes, B.d_batch.bytes));
+    if (B.h_batch.alloc(cap, true) != hipSuccess || B.d_batch.alloc(cap) != hipSuccess)
+      return S->fail(MIPWA_E_NOMEM, "batch buffer allocation failed");
+  }
+  char* hb = B.h_batch.as<char>();
+  char* db = B.d_batch.as<char>();
+  for (const Group& g : groups) {
+    std::memcpy(hb + g.o_map, g.map.data(), g.map.size() * sizeof(int2));
+    std::memcpy(hb + g.o_task, g.tasks.data(), g.tasks.size() * sizeof(int2));
+    Segment* sg = reinterpret_cast<Segment*>(hb + g.o_seg);
+    Job* jb = reinterpret_cast<Job*>(hb + g.o_job);
+    std::memset(sg, 0, (size_t)2 * g.nj * sizeof(Segment));
+    std::memset(jb, 0, (size_t)g.nj * sizeof(Job));
+    for (int j = 0; j < g.nj; ++j) {
+      SJob* J = batch[g.jobs[j]];
+      std::memcpy(hb + g.o_tab[j], J->staged.data(), J->staged.size());
       const PointSet* ps[2] = {&J->ev, &J->norm->ps};
       const int nbs[2] = {J->nb_d, J->nb_q};
       for (int k = 0; k < 2; ++k) {
@@ -516,7 +574,7 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
         s.w = k ? ps[k]->w.p : nullptr;
         s.cache = ps[k]->cache.p;
         s.tiles = ps[k]->tiles.as<Tile>();
-        s.table = db + o_tab[j];
+        s.table = db + g.o_tab[j];
         s.records = J->d_rec.as<double>() + (size_t)(k ? J->nb_d : 0) * J->rs;
         s.n = ps[k]->n;
         s.n_tiles = ps[k]->n_tiles;
@@ -535,9 +593,10 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
         s.g0 = k ? J->G_d : 0;
       }
       Job& q = jb[j];
-      q.tab64 = reinterpret_cast<const double*>(db + o_th[j]);
+      q.tab64 = reinterpret_cast<const double*>(db + g.o_th[j]);
       q.consts = J->d_consts.as<double>();
-      q.out = S->h_res_dev + res_of[J];
+      q.out = B.h_res_dev + st.res_off[g.jobs[j]];
+      q.seq_out = B.h_seq_dev + g.jobs[j];
       q.grec = J->d_grec.as<double>();
       q.n_ev = (double)J->ev.n;
       q.c_eps = 0.0;
@@ -548,42 +607,131 @@ int run_batch(mipwa_server* S, std::vector<SJob*>& batch) {
       q.rs = J->rs;
       q.otf = 0;
     }
-    if (launch_upload(db, S->h_batch.dev, off, S->stream) != hipSuccess)
-      return S->fail(MIPWA_E_HIP, "batch upload failed");
-    const ModelHost& mh0 = js[0]->mh;
-    double step_bytes = 0.0;  // event streams of the step (the normalisation enters as per-cell moments)
-    for (int j = 0; j < nj; ++j) step_bytes += (double)js[j]->ev.n * (2 + 2 * R) * (S->fp64 ? 8.0 : 4.0);
-    if (launch_eval(S->fp64, R, false, reinterpret_cast<const Segment*>(db + o_seg),
-                    reinterpret_cast<const int2*>(db + o_map), reinterpret_cast<const Job*>(db + o_job),
-                    (int)map.size(), kServeWaves, max_nint,
-                    S->fp64 ? (const void*)&mh0.kin64 : (const void*)&mh0.kin32, nullptr, sweep_parts(step_bytes),
-                    S->sweep_order,
+  }
+  // a sampled step: fold the previous sample (complete unless its step is the one in flight) and
+  // bracket this step's kernels
+  st.timed = S->ev_step[0] && st.seq % kStepTimingPeriod == 0;
+  std::unique_lock<std::mutex> tl(S->timing_mu, std::defer_lock);
+  if (st.timed) {
+    tl.lock();
+    if (S->step_timed_unread) {
+      float ms = 0;
+      if (hipEventQuery(S->ev_step[1]) == hipSuccess &&
+          hipEventElapsedTime(&ms, S->ev_step[0], S->ev_step[1]) == hipSuccess) {
+        S->step_dev_ms += ms;
+        S->n_step_timed += 1;
+      }
+      (void)hipGetLastError();
+    }
+    S->step_timed_unread = false;
+    if (hipEventRecord(S->ev_step[0], S->stream) != hipSuccess) return S->fail(MIPWA_E_HIP, "step timing event");
+  }
+  if (launch_upload(db, B.h_batch.dev, off, S->stream) != hipSuccess)
+    return S->fail(MIPWA_E_HIP, "batch upload failed");
+  for (const Group& g : groups) {
+    const ModelHost& mh0 = batch[g.jobs[0]]->mh;
+    if (launch_eval(S->fp64, g.R, false, reinterpret_cast<const Segment*>(db + g.o_seg),
+                    reinterpret_cast<const int2*>(db + g.o_map), reinterpret_cast<const Job*>(db + g.o_job),
+                    (int)g.map.size(), kServeWaves, g.max_nint,
+                    S->fp64 ? (const void*)&mh0.kin64 : (const void*)&mh0.kin32, nullptr, 1, S->sweep_order,
                     S->stream) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batched likelihood kernel failed");
-    if (launch_reduce(reinterpret_cast<const Segment*>(db + o_seg), reinterpret_cast<const Job*>(db + o_job),
-                      reinterpret_cast<const int2*>(db + o_task), (int)tasks.size(), nj, nullptr, S->stream) != hipSuccess)
+    if (launch_reduce(reinterpret_cast<const Segment*>(db + g.o_seg), reinterpret_cast<const Job*>(db + g.o_job),
+                      reinterpret_cast<const int2*>(db + g.o_task), (int)g.tasks.size(), g.nj, nullptr, S->stream,
+                      st.seq) != hipSuccess)
       return S->fail(MIPWA_E_HIP, "batched reduction kernels failed");
-    S->sweep_order ^= 1;
-    const auto t_l = Clock::now();
-    // spin on the stream (the scheduler has nothing else to do meanwhile): a blocking wait wakes up
-    // late while the host is busy with the jobs' threads
-    hipError_t q;
-    while ((q = hipStreamQuery(S->stream)) == hipErrorNotReady) _mm_pause();
-    if (q != hipSuccess) return S->fail(MIPWA_E_HIP, std::string("batch failed: ") + hipGetErrorString(q));
-    S->t_gpu += std::chrono::duration<double>(Clock::now() - t_l).count();
   }
-  const double* res = S->h_res.as<double>();
-  for (SJob* J : batch) {
-    const double* o = res + res_of[J];
+  S->sweep_order ^= 1;
+  if (st.timed) {
+    if (hipEventRecord(S->ev_step[1], S->stream) != hipSuccess) return S->fail(MIPWA_E_HIP, "step timing event");
+    S->step_timed_unread = true;
+  }
+  return MIPWA_OK;
+}
+
+// Wait for a launched step's results: spin on the jobs' sequence words, which flip as soon as the
+// finish has written each job's results, without waiting for the stream's completion signal.  The
+// stream is queried now and then so that a failed launch is still reported.
+int wait_step(mipwa_server* S, Step& st) {
+  mipwa_server::StepBufs& B = S->bufs[st.buf];
+  const unsigned long long* words = B.h_seq.as<unsigned long long>();
+  for (size_t i = 0; i < st.batch.size(); ++i) {
+    const unsigned long long* w = words + i;
+    for (unsigned long long it = 1; __atomic_load_n(w, __ATOMIC_ACQUIRE) != st.seq; ++it) {
+      if ((it & 1023) == 0) {
+        const hipError_t q = hipStreamQuery(S->stream);
+        if (q == hipSuccess && __atomic_load_n(w, __ATOMIC_ACQUIRE) != st.seq)
+          return S->fail(MIPWA_E_HIP, "a step ended without publishing its results");
+        if (q != hipSuccess && q != hipErrorNotReady)
+          return S->fail(MIPWA_E_HIP, std::string("batch failed: ") + hipGetErrorString(q));
+      }
+      _mm_pause();
+    }
+  }
+  const double* res = B.h_res.as<double>();
+  for (size_t i = 0; i < st.batch.size(); ++i) {
+    SJob* J = st.batch[i];
+    const double* o = res + st.res_off[i];
     J->f = o[0];
     J->g.assign(o + 1, o + 1 + J->mh.P);
   }
   return MIPWA_OK;
 }
 
+// Whether every job of a launched step has its results (non-blocking).
+bool step_ready(mipwa_server* S, const Step& st) {
+  const unsigned long long* words = S->bufs[st.buf].h_seq.as<unsigned long long>();
+  for (size_t i = 0; i < st.batch.size(); ++i)
+    if (__atomic_load_n(words + i, __ATOMIC_ACQUIRE) != st.seq) return false;
+  return true;
+}
+
+// Hand a waited-for step's results (or its failure) back to its jobs' threads.
+void hand_back(mipwa_server* S, Step& st, int rc) {
+  const std::string step_err = rc ? S->last_error() : std::string();
+  for (SJob* J : st.batch) {
+    {
+      std::lock_guard<std::mutex> jl(J->m);
+      if (rc) {
+        J->f = NAN;
+        J->step_rc = rc;
+        J->step_err = step_err;
+      }
+      J->done = true;
+    }
+    J->cv.notify_one();
+  }
+}
+
+
 void sched_loop(mipwa_server* S) {
   (void)hipSetDevice(S->device);
+  // Up to two steps in flight on the stream.  While one runs, the jobs of the other (whose results
+  // have been handed back) compute their next points and the next step is formed and queued behind
+  // the running one, so the host's share of a step overlaps the device's.  A step formed while none is
+  // in flight takes at most half of the active jobs: the rest form the next step at once, which splits
+  // the jobs into two groups that then alternate.
+  std::deque<Step> flight;
   std::unique_lock<std::mutex> lk(S->mu);
+  auto finish_oldest = [&]() {
+    Step st = std::move(flight.front());
+    flight.pop_front();
+    lk.unlock();
+    const auto t_g = Clock::now();
+    const int rc = wait_step(S, st);
+    S->t_gpu += std::chrono::duration<double>(Clock::now() - t_g).count();
+    lk.lock();
+    for (SJob* J : st.batch) J->inflight = false;
+    S->n_inflight -= (int)st.batch.size();
+    S->steps += 1;
+    S->batch_sum += (double)st.batch.size();
+    lk.unlock();
+    const auto t_e = Clock::now();
+    hand_back(S, st, rc);
+    lk.lock();
+    S->t_wake += std::chrono::duration<double>(Clock::now() - t_e).count();
+    if (S->steps % 256 == 1) trace(S, "step %lld: batch %zu of %d active", S->steps, st.batch.size(), S->n_active);
+  };
   while (!S->stop) {
     const auto t_0 = Clock::now();
     admit(S);
@@ -595,58 +743,71 @@ void sched_loop(mipwa_server* S) {
       SJob* J = S->queue.front();
       return J->cancel || S->running == 0 || S->used + J->bytes <= S->budget;
     };
-    const auto t_a = Clock::now();
-    S->cv_sched.wait(lk, [&] { return S->stop || S->n_req > 0 || admissible(); });
-    if (S->stop) break;
-    if (S->n_req == 0) continue;
-    // batching window: until every active job has asked, or kBatchWindowUs after the first request
+    if (flight.empty()) {
+      const auto t_a = Clock::now();
+      S->cv_sched.wait(lk, [&] { return S->stop || S->n_req > 0 || admissible(); });
+      S->t_idle += std::chrono::duration<double>(Clock::now() - t_a).count();
+      if (S->stop) break;
+      if (S->n_req == 0) continue;
+    } else if (flight.size() == 2) {
+      finish_oldest();
+      continue;
+    } else {
+      // one step in flight: form the next as soon as a job outside it asks, else hand back its results
+      const auto t_a = Clock::now();
+      while (!S->stop && S->n_req == 0 && !step_ready(S, flight.front()))
+        S->cv_sched.wait_for(lk, std::chrono::microseconds(20));
+      S->t_idle += std::chrono::duration<double>(Clock::now() - t_a).count();
+      if (S->stop) break;
+      if (S->n_req == 0) {
+        finish_oldest();
+        continue;
+      }
+    }
+    // batching window: until every active job outside the steps in flight has asked, or
+    // kBatchWindowUs after this point
     const auto t_b = Clock::now();
     const auto deadline = t_b + std::chrono::microseconds(kBatchWindowUs);
-    while (!S->stop && S->n_req < S->n_active)
+    while (!S->stop && S->n_req < S->n_active - S->n_inflight)
       if (S->cv_sched.wait_until(lk, deadline) == std::cv_status::timeout) break;
     if (S->stop) break;
-    const auto t_c = Clock::now();
-    S->t_idle += std::chrono::duration<double>(t_b - t_a).count();
-    S->t_window += std::chrono::duration<double>(t_c - t_b).count();
-    std::vector<SJob*> batch;
+    S->t_window += std::chrono::duration<double>(Clock::now() - t_b).count();
+    const size_t cap = flight.empty() && S->n_active >= 2 ? (size_t)(S->n_active + 1) / 2 : (size_t)S->n_active;
+    Step st;
+    st.buf = S->next_buf;
     for (auto& kv : S->jobs) {
       SJob* J = kv.second.get();
+      if (st.batch.size() >= cap) break;
       if (J->state != ACTIVE || !J->req || J->inflight) continue;
       J->req = false;
       S->n_req -= 1;
       if (J->cancel) continue;  // its worker withdraws
       J->inflight = true;
-      batch.push_back(J);
+      st.batch.push_back(J);
     }
-    if (batch.empty()) continue;
+    if (st.batch.empty()) continue;
+    S->n_inflight += (int)st.batch.size();
     lk.unlock();
-    const double gpu0 = S->t_gpu;
     const auto t_d = Clock::now();
-    const int rc = run_batch(S, batch);
-    S->t_stage += std::chrono::duration<double>(Clock::now() - t_d).count() - (S->t_gpu - gpu0);
+    const bool overlapped = !flight.empty();
+    const int rc = launch_step(S, st);
+    S->t_stage += std::chrono::duration<double>(Clock::now() - t_d).count();
     lk.lock();
-    for (SJob* J : batch) J->inflight = false;
-    S->steps += 1;
-    S->batch_sum += (double)batch.size();
-    lk.unlock();
-    const std::string step_err = rc ? S->last_error() : std::string();
-    const auto t_e = Clock::now();
-    for (SJob* J : batch) {
-      {
-        std::lock_guard<std::mutex> jl(J->m);
-        if (rc) {
-          J->f = NAN;
-          J->step_rc = rc;
-          J->step_err = step_err;
-        }
-        J->done = true;
-      }
-      J->cv.notify_one();
+    if (rc) {
+      // nothing of this step runs: its jobs end with the failure
+      for (SJob* J : st.batch) J->inflight = false;
+      S->n_inflight -= (int)st.batch.size();
+      lk.unlock();
+      hand_back(S, st, rc);
+      lk.lock();
+      continue;
     }
-    lk.lock();
-    S->t_wake += std::chrono::duration<double>(Clock::now() - t_e).count();
-    if (S->steps % 256 == 1) trace(S, "step %lld: batch %zu of %d active", S->steps, batch.size(), S->n_active);
+    S->next_buf ^= 1;
+    if (overlapped) S->n_overlapped += 1;
+    flight.push_back(std::move(st));
   }
+  // stopping: the steps in flight still end, and their jobs get their results
+  while (!flight.empty()) finish_oldest();
 }
 
 }  // namespace
@@ -666,18 +827,29 @@ int mipwa_server_create(int device, int precision, size_t budget, mipwa_server**
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)64 << 30;
   S->budget = budget ? budget : (size_t)(0.8 * (double)free_b);
-  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&S->ev_step[0]) != hipSuccess || hipEventCreate(&S->ev_step[1]) != hipSuccess) {
+    for (hipEvent_t e : S->ev_step)
+      if (e) (void)hipEventDestroy(e);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
     return MIPWA_E_HIP;
   }
   // step buffers sized up front for a few hundred jobs per step: allocating pinned or device memory
   // during the steps costs milliseconds each time (they still grow if a step needs more)
-  if (S->h_batch.alloc(kBatchBytes0, true) != hipSuccess || S->d_batch.alloc(kBatchBytes0) != hipSuccess ||
-      S->h_res.alloc(kResultBytes0, true) != hipSuccess ||
-      hipHostGetDevicePointer((void**)&S->h_res_dev, S->h_res.p, 0) != hipSuccess) {
-    (void)hipStreamDestroy(S->stream);
-    delete S;
-    return MIPWA_E_NOMEM;
+  for (auto& B : S->bufs) {
+    if (B.h_batch.alloc(kBatchBytes0, true) != hipSuccess || B.d_batch.alloc(kBatchBytes0) != hipSuccess ||
+        B.h_res.alloc(kResultBytes0, true) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&B.h_res_dev, B.h_res.p, 0) != hipSuccess ||
+        B.h_seq.alloc(kSeqBytes0, true) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&B.h_seq_dev, B.h_seq.p, 0) != hipSuccess) {
+      for (hipEvent_t e : S->ev_step)
+        if (e) (void)hipEventDestroy(e);
+      (void)hipStreamDestroy(S->stream);
+      delete S;
+      return MIPWA_E_NOMEM;
+    }
+    std::memset(B.h_seq.p, 0, B.h_seq.bytes);
   }
   S->sched = std::thread(sched_loop, S);
   *out = S;
@@ -826,6 +998,18 @@ int mipwa_server_stats(mipwa_server* S, mipwa_serve_stats* st) {
   st->peak_bytes = (int64_t)S->peak;
   st->steps = S->steps;
   st->mean_batch = S->steps ? S->batch_sum / S->steps : 0.0;
+  std::lock_guard<std::mutex> tl(S->timing_mu);
+  if (S->step_timed_unread) {  // the last sample: its step has long finished unless a step is running
+    float ms = 0;
+    if (hipEventQuery(S->ev_step[1]) == hipSuccess && hipEventElapsedTime(&ms, S->ev_step[0], S->ev_step[1]) == hipSuccess) {
+      S->step_dev_ms += ms;
+      S->n_step_timed += 1;
+      S->step_timed_unread = false;
+    }
+    (void)hipGetLastError();
+  }
+  st->step_device_s = S->n_step_timed ? 1e-3 * S->step_dev_ms / S->n_step_timed : 0.0;
+  st->device_busy = span > 0 ? st->step_device_s * S->steps / span : 0.0;
   return MIPWA_OK;
 }
 
@@ -850,13 +1034,15 @@ void mipwa_server_destroy(mipwa_server* S) {
   if (S->sched.joinable()) S->sched.join();
   for (auto& kv : S->jobs)
     if (kv.second->worker.joinable()) kv.second->worker.join();
-  trace(S, "scheduler: %lld steps; idle %.3f s, batching window %.3f s, staging %.3f s, launch to results %.3f s, "
-        "results to the jobs %.3f s, admission and joins %.3f s",
-        S->steps, S->t_idle, S->t_window, S->t_stage, S->t_gpu, S->t_wake, S->t_admit);
+  trace(S, "scheduler: %lld steps (%lld launched behind another); idle %.3f s, batching window %.3f s, staging "
+        "and launch %.3f s, waiting for results %.3f s, results to the jobs %.3f s, admission and joins %.3f s",
+        S->steps, S->n_overlapped, S->t_idle, S->t_window, S->t_stage, S->t_gpu, S->t_wake, S->t_admit);
   (void)hipSetDevice(S->device);
   (void)hipStreamSynchronize(S->stream);
   S->jobs.clear();
   S->norms.clear();
+  for (hipEvent_t e : S->ev_step)
+    if (e) (void)hipEventDestroy(e);
   (void)hipStreamDestroy(S->stream);
   delete S;
 }
