@@ -8,10 +8,11 @@
 // points are cell-sorted once per knot grid and shared; with the shapes fixed, each evaluation takes
 // the normalisation integral as a quadratic form over the job's moments instead of a sweep over the
 // points.  Every evaluation a job asks for is posted to the scheduler, which gathers the pending
-// evaluations of all active jobs into one launch of the streaming kernel (one data segment and one
-// cell segment per job).  Jobs that become active while a step
-// runs join the next step.  A job's block count depends only on its own sizes, so its reduction
-// order, and therefore its result, is bitwise the same alone or in any mix.
+// evaluations of active jobs into one launch of the streaming kernel (one data segment and one cell
+// segment per job).  Up to two such steps are in flight on the server's stream, so that one group of
+// jobs computes its next points while the other's step runs.  A job's block count depends only on
+// its own sizes and every job is swept in one part, so its reduction order, and therefore its result,
+// is bitwise the same alone or in any mix.
 #include <hip/hip_runtime.h>
 #include <immintrin.h>
 
