@@ -192,6 +192,37 @@ def oracle_leg(wl, table, events, norm, mixed, reps=1):
     return cpu, vs
 
 
+def headline_fit_mixed_vs_fp64(wl, table, events, norm):
+    """The headline sample fitted in mixed precision and in FP64 by the library, from the same start:
+    the largest |d theta| / sigma over the floated parameters (sigma from the FP64 fit's Hessian).  An
+    oracle fit of 10M + 10M points would take minutes; the FP64 path stands in for it (it agrees with
+    the oracle to 1e-10 in -2 ln L and 1e-8 in the gradient at this size)."""
+    from paper_1703_03284_amd import FP64, MIXED, context_for
+    d = wl.decay
+    res = {}
+    for name, prec in (("fp64", FP64), ("mixed", MIXED)):
+        ctx = context_for(d, wl.knots(), wl.resonances, prec)
+        if table is not None:
+            ctx.set_eff_table(table, d.smin, d.smax)
+        ctx.load_events(*events)
+        ctx.load_norm(*norm)
+        t0 = time.perf_counter()
+        res[name] = (ctx.fit(wl.start(), fixed=wl.fixed(), tol_edm=1e-6, raise_noconv=False),
+                     time.perf_counter() - t0)
+        ctx.close()
+    (f64, t64), (f32, t32) = res["fp64"], res["mixed"]
+    free = np.flatnonzero(wl.fixed() == 0)
+    dth = f32.theta - f64.theta
+    npair = wl.n_knots + wl.n_res
+    dth[1:2 * npair:2] = np.angle(np.exp(1j * dth[1:2 * npair:2]))
+    ratio = f32.sigma[free] / f64.sigma[free]
+    return {"fit_theta_max_sigma_vs_fp64": float(np.max(np.abs(dth[free]) / f64.sigma[free])),
+            "sigma_ratio_min": float(ratio.min()), "sigma_ratio_max": float(ratio.max()),
+            "nll_mixed_minus_fp64": f32.nll - f64.nll, "status": [f64.status, f32.status],
+            "evals": [f64.n_eval, f32.n_eval], "fit_s": [round(t64, 3), round(t32, 3)],
+            "floated": int(len(free))}
+
+
 def small_fit_vs_oracle():
     """The 10k-event fit workload fitted by the library in mixed precision and by the oracle (scipy
     BFGS, V = 2 H^-1) from the same start on the same toy: the largest |d theta| / sigma over the
@@ -551,6 +582,8 @@ def main():
         log(f"[bench] oracle on the headline inputs: {cpu}; {vs}")
         vs["small_fit"] = small_fit_vs_oracle()
         log(f"[bench] small fit against the oracle's: {vs['small_fit']}")
+        vs["headline_fit"] = headline_fit_mixed_vs_fp64(wl, table, events, norm)
+        log(f"[bench] headline fit, mixed against FP64: {vs['headline_fit']}")
         out["vs_oracle"] = vs
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -251,8 +251,9 @@ int mipwa_timing_stats(const mipwa_ctx* ctx, int64_t* count, double* mean_total_
 
 /* Measured streaming-read ceiling of a GPU, the denominator beside the datasheet peak when the
  * likelihood sweep's bandwidth is reported: a buffer of `bytes` (>= 1 MiB) is read with 16-byte
- * non-temporal loads and no other work, `reps` times after one warm-up; *gbs receives the best rate in
- * GB/s.  Allocates and frees its own buffer.  Errors: E_INVAL, E_NOMEM, E_HIP. */
+ * non-temporal loads and no other work, `reps` times for each of four grid sizes (4 to 32 blocks of 256
+ * threads per CU) after one warm-up; *gbs receives the best rate in GB/s.  Allocates and frees its own
+ * buffer.  Errors: E_INVAL, E_NOMEM, E_HIP. */
 int mipwa_read_bandwidth(int device, int64_t bytes, int reps, double* gbs);
 
 /* Launch shape of the streaming kernel: blocks (0 = default) and waves per block (0 = default, 1..16).

@@ -45,7 +45,8 @@ extern "C" int mipwa_read_bandwidth(int device, int64_t bytes, int reps, double*
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return MIPWA_E_HIP;
   const long long n = bytes / 16;
-  const int blocks = 8 * std::max(prop.multiProcessorCount, 1);
+  const int cus = std::max(prop.multiProcessorCount, 1);
+  const int blocks = 32 * cus;  // the most grid the probe tries (blocks of 256 threads)
   void *a = nullptr, *out = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipStream_t st = nullptr;
@@ -58,16 +59,19 @@ extern "C" int mipwa_read_bandwidth(int device, int64_t bytes, int reps, double*
   } else {
     k_fill<<<blocks, 256, 0, st>>>(static_cast<float4*>(a), n);
     k_read<<<blocks, 256, 0, st>>>(static_cast<const float4*>(a), n, static_cast<float*>(out));  // warm-up
+    // the best over grids of 4, 8, 16 and 32 blocks per CU
     float best = 0.0f;
-    for (int r = 0; r < reps && rc == MIPWA_OK; ++r) {
-      float ms = 0.0f;
-      if (hipEventRecord(e0, st) != hipSuccess) rc = MIPWA_E_HIP;
-      k_read<<<blocks, 256, 0, st>>>(static_cast<const float4*>(a), n, static_cast<float*>(out));
-      if (hipGetLastError() != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
-          hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-        rc = MIPWA_E_HIP;
-      else if (r == 0 || ms < best)
-        best = ms;
+    for (int g = 4; g <= 32 && rc == MIPWA_OK; g *= 2) {
+      for (int r = 0; r < reps && rc == MIPWA_OK; ++r) {
+        float ms = 0.0f;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = MIPWA_E_HIP;
+        k_read<<<g * cus, 256, 0, st>>>(static_cast<const float4*>(a), n, static_cast<float*>(out));
+        if (hipGetLastError() != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+          rc = MIPWA_E_HIP;
+        else if (best == 0.0f || ms < best)
+          best = ms;
+      }
     }
     if (rc == MIPWA_OK) *gbs = (double)n * 16.0 / (best * 1e-3) / 1e9;
   }
