@@ -722,8 +722,10 @@ __global__ __launch_bounds__(kMomChunk) void k_moments(Segment sg, const Tile* _
 
 // fin: the reduced data record followed by the reduced normalisation record (LDS); kc: the job's
 // Thomas factors and interval widths staged in LDS (the solve below is a serial chain, so its
-// operands must not come from global memory one dependent load at a time).
-__device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fin, const double* kc,
+// operands must not come from global memory one dependent load at a time); th: the knot and
+// coefficient parameters, staged in LDS with them.  The results are gathered in LDS and written out
+// by the first wave, which alone then needs a fence before the sequence word is published.
+__device__ void finish_job(const Job& jb, const double* fin, const double* kc, const double* th,
                            unsigned long long seq, double* out) {
   const int N = jb.N, nint = N - 1, R = jb.R;
   const double* fd = fin;
@@ -731,7 +733,7 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
   const int s0 = 8 * nint;
   const double I = fn[s0];
   const double scale = jb.n_ev / I;
-  const double* th = jb.tab64 ? jb.tab64 : (const double*)((const char*)targ.w + jb.theta_off);
+  __shared__ double ob[1 + 2 * kMaxKnots + 4 * kMaxRes];
   const double* thc = kc;                // Thomas factors c'_i of the interior system
   const double* thinv = thc + (N - 2);   // 1 / pivot_i
   const double* h = thinv + (N - 2);
@@ -771,31 +773,51 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
   }
   __syncthreads();
   // M = T^-1 D z on the interior knots, T symmetric tridiagonal: the z-partials through M are
-  // D^T T^-1 g_M.  One Thomas solve per component (re on wave 0, im on wave 1, or both on thread 0
-  // of a one-wave block).
+  // D^T T^-1 g_M.  The Thomas solve of the n interior rows is two first-order linear recurrences,
+  //   forward   y_i = A_i + B_i y_{i-1},  A_i = g_i / p_i,  B_i = -h_i / p_i,  y_{-1} = 0,
+  //   backward  x_i = y_i + C_i x_{i+1},  C_i = -c'_i,  x_n = 0,
+  // each taken as a scan of affine maps over the 64 lanes of one wave (re on wave 0, im on wave 1):
+  // lane l composes its rows 2l and 2l + 1, six shuffle rounds compose the lanes' maps in a fixed
+  // order, and the row a lane's map skips is filled in from its neighbour's result.
   const int n = N - 2;
-  for (int comp = (threadIdx.x >> 6); comp < 2 && (threadIdx.x & 63) == 0;
-       comp += (blockDim.x >= 128 ? 2 : 1)) {
-    // both sweeps carry their chain in a register and have no branch in the body, so the loads of
-    // the independent operands (LDS) are issued ahead of the dependent arithmetic
-    double prev = 0.0;
-    if (n > 0) {
-      prev = gm[2 + comp] * thinv[0];
-      u[2 + comp] = prev;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < 2) {
+    const int comp = wave;
+    const int i0 = 2 * lane, i1 = 2 * lane + 1;
+    const double A0 = i0 < n ? gm[2 * (i0 + 1) + comp] * thinv[i0] : 0.0;
+    const double B0 = i0 < n && i0 > 0 ? -h[i0] * thinv[i0] : 0.0;
+    const double A1 = i1 < n ? gm[2 * (i1 + 1) + comp] * thinv[i1] : 0.0;
+    const double B1 = i1 < n ? -h[i1] * thinv[i1] : 0.0;
+    double P = A1 + B1 * A0, Q = B1 * B0;  // y_{i1} = P + Q y_{i0 - 1}
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const double Pe = __shfl_up(P, d), Qe = __shfl_up(Q, d);  // the map of the rows before
+      if (lane >= d) {
+        P = P + Q * Pe;
+        Q = Q * Qe;
+      }
     }
-#pragma unroll 8
-    for (int i = 1; i < n; ++i) {
-      prev = (gm[2 * (i + 1) + comp] - h[i] * prev) * thinv[i];
-      u[2 * (i + 1) + comp] = prev;
+    const double yb = __shfl_up(P, 1);  // y_{i0 - 1}, the previous lane's last row
+    const double Y0 = i0 < n ? A0 + B0 * (lane > 0 ? yb : 0.0) : 0.0;
+    const double Y1 = i1 < n ? P : 0.0;
+    const double C0 = i0 < n - 1 ? -thc[i0] : 0.0;
+    const double C1 = i1 < n - 1 ? -thc[i1] : 0.0;
+    double X = Y0 + C0 * Y1, Z = C0 * C1;  // x_{i0} = X + Z x_{i1 + 1}
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const double Xa = __shfl_down(X, d), Za = __shfl_down(Z, d);  // the map of the rows after
+      if (lane + d < 64) {
+        X = X + Z * Xa;
+        Z = Z * Za;
+      }
     }
-    double next = prev;
-#pragma unroll 8
-    for (int i = n - 2; i >= 0; --i) {
-      next = u[2 * (i + 1) + comp] - thc[i] * next;
-      u[2 * (i + 1) + comp] = next;
+    const double xa = __shfl_down(X, 1);  // x_{i1 + 1}, the next lane's first row
+    if (i0 < n) u[2 * (i0 + 1) + comp] = X;
+    if (i1 < n) u[2 * (i1 + 1) + comp] = Y1 + C1 * (lane < 63 ? xa : 0.0);
+    if (lane == 0) {
+      u[comp] = 0.0;
+      u[2 * (N - 1) + comp] = 0.0;
     }
-    u[comp] = 0.0;
-    u[2 * (N - 1) + comp] = 0.0;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
@@ -820,11 +842,11 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
       const double a = th[2 * k], ph = th[2 * k + 1];
       double sn, cs;
       sincos(ph, &sn, &cs);
-      out[1 + 2 * k] = yr * cs + yi * sn;
-      out[2 + 2 * k] = a * (-yr * sn + yi * cs);
+      ob[1 + 2 * k] = yr * cs + yi * sn;
+      ob[2 + 2 * k] = a * (-yr * sn + yi * cs);
     } else if (jb.swave == kSwaveCartesian) {
-      out[1 + 2 * k] = yr;
-      out[2 + 2 * k] = yi;
+      ob[1 + 2 * k] = yr;
+      ob[2 + 2 * k] = yi;
     } else {
       gy[2 * k] = yr;  // isobar: combined below
       gy[2 * k + 1] = yi;
@@ -840,20 +862,21 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
       const double cm = 2.0 * th[0], ph = th[1];
       double sn, cs;
       sincos(ph, &sn, &cs);
-      out[1] = 0.5 * (yr * cs + yi * sn);
-      out[2] = 0.5 * cm * (-yr * sn + yi * cs);
+      ob[1] = 0.5 * (yr * cs + yi * sn);
+      ob[2] = 0.5 * cm * (-yr * sn + yi * cs);
     }
   }
   // external offset of the resonance block: after the knots, or after c_NR
   const int o = jb.swave == kSwaveIsobar ? 2 : 2 * N;
-  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+  // the resonances on wave 2 and -2 ln L on wave 3, beside the knots on waves 0 and 1
+  for (int r = threadIdx.x - 128; r >= 0 && r < R; r += 64) {
     const double gr = fd[s0 + 1 + 2 * r] + scale * fn[s0 + 1 + 2 * r];
     const double gi = fd[s0 + 2 + 2 * r] + scale * fn[s0 + 2 + 2 * r];
     const double cm = th[2 * N + 2 * r], ca = th[2 * N + 2 * r + 1];
     double sn, cs;
     sincos(ca, &sn, &cs);
-    out[1 + o + 2 * r] = gr * cs + gi * sn;
-    out[2 + o + 2 * r] = cm * (-gr * sn + gi * cs);
+    ob[1 + o + 2 * r] = gr * cs + gi * sn;
+    ob[2 + o + 2 * r] = cm * (-gr * sn + gi * cs);
     double dm = 0.0, dg = 0.0;
     if (jb.otf) {
       const int om = s0 + 1 + 2 * R + 2 * r, og = s0 + 1 + 4 * R + 2 * r;
@@ -863,15 +886,21 @@ __device__ void finish_job(const Job& jb, const ArgTable& targ, const double* fi
       dm = cr * hmr + ci * hmi;
       dg = cr * hgr + ci * hgi;
     }
-    out[1 + o + 2 * R + 2 * r] = dm;
-    out[2 + o + 2 * R + 2 * r] = dg;
+    ob[1 + o + 2 * R + 2 * r] = dm;
+    ob[2 + o + 2 * R + 2 * r] = dg;
   }
-  if (threadIdx.x == 0) out[0] = -2.0 * fd[s0] + jb.c_eps + 2.0 * jb.n_ev * log(I);
-  __threadfence_system();
-  if (jb.seq_out) {
-    // every thread's results are out; the sequence number tells a polling host they are complete
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(jb.seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (threadIdx.x == 192) ob[0] = -2.0 * fd[s0] + jb.c_eps + 2.0 * jb.n_ev * log(I);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int nout = 1 + o + 4 * R;
+    for (int i = threadIdx.x; i < nout; i += 64) out[i] = ob[i];
+    if (jb.seq_out) {
+      // The results may sit in host memory that a host thread polls: the wave's stores are made
+      // visible system-wide before the sequence number that tells the host they are complete.
+      // Results in device memory need no fence: the kernel's end orders them before later work.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      if (threadIdx.x == 0) __hip_atomic_store(jb.seq_out, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -962,6 +991,7 @@ __global__ __launch_bounds__(512) void k_group_sum(const Segment* __restrict__ s
 constexpr int kMaxRecord = 8 * (kMaxKnots - 1) + 1 + 6 * kMaxRes;
 
 constexpr int kMaxConsts = 3 * kMaxKnots - 5;
+constexpr int kMaxTheta = 2 * kMaxKnots + 2 * kMaxRes;  // knot pairs and coefficient pairs
 constexpr int kFinishThreads = 512;
 
 // One block of kFinishThreads per job.  `jobs` == nullptr: a single job passed by value in `one`
@@ -970,16 +1000,17 @@ __global__ __launch_bounds__(kFinishThreads) void k_job_finish(const Job* __rest
                                                               unsigned long long seq, double* out_override) {
   __shared__ double fin[2 * kMaxRecord];
   __shared__ double kc[kMaxConsts];
+  __shared__ double thl[kMaxTheta];
   const Job jb = jobs ? jobs[blockIdx.x] : one;
-  const int rs = jb.rs, nf = 2 * rs, nkc = 3 * jb.N - 5;
-  // the constants are requested first; they are only needed once the records are summed
-  constexpr int KPT = (kMaxConsts + kFinishThreads - 1) / kFinishThreads;
-  double kcv[KPT];
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const int i = threadIdx.x + j * kFinishThreads;
-    kcv[j] = i < nkc ? jb.consts[i] : 0.0;
-  }
+  const int rs = jb.rs, nf = 2 * rs, nkc = 3 * jb.N - 5, nth = 2 * jb.N + 2 * jb.R;
+  // the constants and parameters are requested first; they are only needed once the records are summed
+  static_assert(kMaxConsts <= kFinishThreads && kMaxTheta <= kFinishThreads, "one word per thread");
+  static_assert(kFinishThreads >= 256 && kMaxKnots <= 130 && kMaxRes <= 64,
+                "the finish takes the knots on waves 0-1 (128 interior rows at most), resonances on wave 2, "
+                "the log on wave 3");
+  const double* th = jb.tab64 ? jb.tab64 : (const double*)((const char*)targ.w + jb.theta_off);
+  const double kcv = threadIdx.x < nkc ? jb.consts[threadIdx.x] : 0.0;
+  const double thv = threadIdx.x < nth ? th[threadIdx.x] : 0.0;
   // field f < rs of the data groups, then of the normalisation groups.  Each thread takes up to FPT
   // fields at once and issues the loads of eight groups of all of them before adding, so the sums
   // wait on about one memory round trip; each field's groups are added in group order.
@@ -1016,13 +1047,10 @@ __global__ __launch_bounds__(kFinishThreads) void k_job_finish(const Job* __rest
     for (int j = 0; j < FPT; ++j)
       if (f0 + j * blockDim.x < nf) fin[f0 + j * blockDim.x] = sum[j];
   }
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const int i = threadIdx.x + j * kFinishThreads;
-    if (i < nkc) kc[i] = kcv[j];
-  }
+  if (threadIdx.x < nkc) kc[threadIdx.x] = kcv;
+  if (threadIdx.x < nth) thl[threadIdx.x] = thv;
   __syncthreads();
-  finish_job(jb, targ, fin, kc, seq, out_override ? out_override : jb.out);
+  finish_job(jb, fin, kc, thl, seq, out_override ? out_override : jb.out);
 }
 
 // ---------------------------------------------------------------------------------------------
