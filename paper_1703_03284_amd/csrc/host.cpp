@@ -203,11 +203,17 @@ void ModelHost::res_table(const double* theta, double* out) const {
   }
 }
 
-int ModelHost::upload_res64(const double* theta, DevBuf& d) const {
+int ModelHost::upload_res64(const double* theta, DevBuf& d, hipStream_t st) const {
   std::vector<double> r((size_t)kResWords * std::max(R, 1), 0.0);
   res_table(theta, r.data());
   if (d.alloc(r.size() * sizeof(double)) != hipSuccess) return MIPWA_E_NOMEM;
-  if (hipMemcpy(d.p, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return MIPWA_E_HIP;
+  if (st) {
+    if (hipMemcpyAsync(d.p, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return MIPWA_E_HIP;
+  } else if (hipMemcpy(d.p, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    return MIPWA_E_HIP;
+  }
   return MIPWA_OK;
 }
 

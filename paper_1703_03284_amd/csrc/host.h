@@ -17,25 +17,40 @@ namespace mipwa {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  // memory from a stream-ordered pool: released by a free in the order of free_st, which, unlike a
+  // plain free, does not wait for the whole device
+  hipMemPool_t pool = nullptr;
+  hipStream_t free_st = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), pool(o.pool), free_st(o.free_st) {
+    o.p = nullptr;
+    o.bytes = 0;
+    o.pool = nullptr;
+    o.free_st = nullptr;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       bytes = o.bytes;
+      pool = o.pool;
+      free_st = o.free_st;
       o.p = nullptr;
       o.bytes = 0;
+      o.pool = nullptr;
+      o.free_st = nullptr;
     }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)(pool ? hipFreeAsync(p, free_st) : hipFree(p));
     p = nullptr;
     bytes = 0;
+    pool = nullptr;
+    free_st = nullptr;
   }
   hipError_t alloc(size_t n) {
     if (n <= bytes && p) return hipSuccess;
@@ -44,6 +59,21 @@ struct DevBuf {
     if (e == hipSuccess) bytes = n;
     else p = nullptr;
     return e;
+  }
+  // from `pl` in the order of stream `st` (a plain allocation when pl is null); the memory is later
+  // freed in the order of `fst`
+  hipError_t alloc_from(size_t n, hipMemPool_t pl, hipStream_t st, hipStream_t fst) {
+    if (!pl) return alloc(n);
+    release();
+    hipError_t e = hipMallocFromPoolAsync(&p, n ? n : 16, pl, st);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = n;
+    pool = pl;
+    free_st = fst;
+    return hipSuccess;
   }
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
@@ -101,8 +131,9 @@ struct ModelHost {
   void poly_table(const double* theta, double* out) const;
   // per-resonance constants (kResWords doubles each) at the given masses/widths in theta
   void res_table(const double* theta, double* out) const;
-  // FP64 resonance constants at theta into a device buffer (synchronous)
-  int upload_res64(const double* theta, DevBuf& d) const;
+  // FP64 resonance constants at theta into a device buffer (synchronous; the copy is made in the
+  // order of stream st when one is given, for memory allocated in that order)
+  int upload_res64(const double* theta, DevBuf& d, hipStream_t st = nullptr) const;
   int interval(double s) const;
   bool inside(double s12, double s13, double tol) const;
   int check_theta(const double* theta, std::string& err) const;
@@ -128,8 +159,10 @@ struct EffTable {
   bool set() const { return nx > 0; }
 };
 
+// With a pool, the point set's memory and the scratch of the load come from it in the order of st,
+// and the point set's memory is freed in the order of free_st.
 int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, const double* s13, const double* w,
                 const double* eff, long long n, const EffTable& et, hipStream_t st, PointSet& ps,
-                std::string& err);
+                std::string& err, hipMemPool_t pool = nullptr, hipStream_t free_st = nullptr);
 
 }  // namespace mipwa

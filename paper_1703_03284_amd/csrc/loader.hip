@@ -103,12 +103,14 @@ __global__ __launch_bounds__(256) void k_gather(const unsigned* __restrict__ key
 
 int grid_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 4096); }
 
-// Scratch memory of one load, allocated and freed in stream order: a plain free would wait for
-// every stream on the device, including the evaluations of other jobs.
+// Scratch memory of one load, allocated and freed in stream order (from the given pool, else the
+// device's default one): a plain free would wait for every stream on the device, including the
+// evaluations of other jobs.
 struct StreamBuf {
   void* p = nullptr;
   hipStream_t st = nullptr;
-  StreamBuf() = default;
+  hipMemPool_t pool = nullptr;
+  explicit StreamBuf(hipMemPool_t pl) : pool(pl) {}
   StreamBuf(const StreamBuf&) = delete;
   StreamBuf& operator=(const StreamBuf&) = delete;
   ~StreamBuf() {
@@ -116,7 +118,9 @@ struct StreamBuf {
   }
   bool alloc(size_t n, hipStream_t s) {
     st = s;
-    return hipMallocAsync(&p, n ? n : 16, s) != hipSuccess;
+    const hipError_t e = pool ? hipMallocFromPoolAsync(&p, n ? n : 16, pool, s) : hipMallocAsync(&p, n ? n : 16, s);
+    if (e != hipSuccess) p = nullptr;
+    return e != hipSuccess;
   }
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
@@ -133,7 +137,8 @@ struct StreamBuf {
 }  // namespace
 
 int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, const double* s13, const double* w,
-                const double* eff, long long n, const EffTable& et, hipStream_t st, PointSet& ps, std::string& err) {
+                const double* eff, long long n, const EffTable& et, hipStream_t st, PointSet& ps, std::string& err,
+                hipMemPool_t pool, hipStream_t free_st) {
   ps.loaded = false;
   if (n < 1 || !s12 || !s13 || (kind == 1 && !w)) {
     err = kind == 1 ? "need n >= 1 points with s12, s13 and w" : "need n >= 1 events with s12 and s13";
@@ -146,7 +151,8 @@ int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, con
   const int N = mh.N, nint = N - 1;
   const size_t ncell = (size_t)nint * nint;
   (void)hipGetLastError();
-  StreamBuf d12, d13, dw, deff, dkn, dh, da, db, dkey, didx, dkey2, didx2, dstart, dbad;
+  StreamBuf d12(pool), d13(pool), dw(pool), deff(pool), dkn(pool), dh(pool), da(pool), db(pool), dkey(pool),
+      didx(pool), dkey2(pool), didx2(pool), dstart(pool), dbad(pool);
   if (d12.alloc(n * 8, st) || d13.alloc(n * 8, st) || (kind == 1 && dw.alloc(n * 8, st)) ||
       (eff && deff.alloc(n * 8, st)) || dkn.alloc(N * 8, st) || dh.alloc(nint * 8, st) || da.alloc(n * 8, st) ||
       db.alloc(n * 8, st) || dkey.alloc(n * 4, st) || didx.alloc(n * 4, st) || dkey2.alloc(n * 4, st) ||
@@ -188,7 +194,7 @@ int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, con
   }
   // efficiency: given, or looked up in the table at the points as given (not the swapped coordinates)
   const double* d_eps = eff ? deff.as<double>() : nullptr;
-  StreamBuf dlook;
+  StreamBuf dlook(pool);
   if (!eff && et.set()) {
     if (dlook.alloc(n * 8, st)) {
       err = "device allocation failed for the efficiency lookup";
@@ -206,7 +212,7 @@ int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, con
   LCHK(rocprim::radix_sort_pairs(nullptr, temp, dkey.as<unsigned>(), dkey2.as<unsigned>(), didx.as<unsigned>(),
                                  didx2.as<unsigned>(), (size_t)n, 0, end_bit, st),
        "sort setup failed");
-  StreamBuf dtemp;
+  StreamBuf dtemp(pool);
   if (dtemp.alloc(temp, st)) {
     err = "device allocation failed for the sort";
     return MIPWA_E_NOMEM;
@@ -218,9 +224,10 @@ int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, con
   LCHK(hipGetLastError(), "cell start kernel failed");
   // point arrays in sorted order
   const size_t real = fp64 ? 8 : 4;
-  if (ps.tt.alloc(2 * n * real) || ps.ss.alloc(2 * n * 8) ||
-      ps.cache.alloc((size_t)std::max(mh.R, 1) * 2 * n * real) ||
-      (kind == 1 && (ps.w.alloc(n * real) || ps.wplain.alloc(n * real)))) {
+  if (ps.tt.alloc_from(2 * n * real, pool, st, free_st) || ps.ss.alloc_from(2 * n * 8, pool, st, free_st) ||
+      ps.cache.alloc_from((size_t)std::max(mh.R, 1) * 2 * n * real, pool, st, free_st) ||
+      (kind == 1 &&
+       (ps.w.alloc_from(n * real, pool, st, free_st) || ps.wplain.alloc_from(n * real, pool, st, free_st)))) {
     err = "device allocation failed for points";
     return MIPWA_E_NOMEM;
   }
@@ -268,13 +275,16 @@ int load_points(const ModelHost& mh, bool fp64, int kind, const double* s12, con
       tiles.push_back(Tile{(int)(c / nint), (int)(c % nint), (int)t, (int)std::min<long long>(kTile, hi - t)});
     cells.back().count = (int)tiles.size() - cells.back().start;
   }
-  if (ps.tiles.alloc(tiles.size() * sizeof(Tile)) || ps.cells.alloc(std::max<size_t>(cells.size(), 1) * sizeof(Tile))) {
+  if (ps.tiles.alloc_from(tiles.size() * sizeof(Tile), pool, st, free_st) ||
+      ps.cells.alloc_from(std::max<size_t>(cells.size(), 1) * sizeof(Tile), pool, st, free_st)) {
     err = "device allocation failed for tiles";
     return MIPWA_E_NOMEM;
   }
-  LCHK(hipMemcpy(ps.tiles.p, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice), "copy of tiles failed");
-  LCHK(hipMemcpy(ps.cells.p, cells.data(), cells.size() * sizeof(Tile), hipMemcpyHostToDevice),
+  LCHK(hipMemcpyAsync(ps.tiles.p, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st),
+       "copy of tiles failed");
+  LCHK(hipMemcpyAsync(ps.cells.p, cells.data(), cells.size() * sizeof(Tile), hipMemcpyHostToDevice, st),
        "upload of the cell list failed");
+  LCHK(hipStreamSynchronize(st), "upload of the tiles failed");
   if (kind == 0) {
     ps.w.release();
     ps.wplain.release();

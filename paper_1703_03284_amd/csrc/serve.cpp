@@ -51,6 +51,7 @@ constexpr int kStepTimingPeriod = 16;
 constexpr size_t kBatchBytes0 = (size_t)4 << 20;   // initial step descriptor buffer (host and device)
 constexpr size_t kResultBytes0 = (size_t)1 << 20;  // initial result buffer (mapped host memory)
 constexpr size_t kSeqBytes0 = (size_t)64 << 10;    // initial sequence words: 8192 jobs per step
+constexpr int kLoadStreams = 4;                    // streams the jobs' loads are spread over
 
 // Sequence numbers of serving steps, unique in the process: pinned memory handed back by a destroyed
 // server may still hold one of its numbers.
@@ -164,6 +165,12 @@ struct mipwa_server {
   bool fp64 = false;
   size_t budget = 0;
   hipStream_t stream = nullptr;
+  // Device memory of the jobs and the normalisation sets: a stream-ordered pool that keeps what is
+  // freed, so that loading and retiring jobs neither waits for the device (as a plain free does,
+  // stalling every other job's loads and the steps' launches) nor returns memory to the driver.
+  // A job's memory is freed in the order of `stream`, after every step that may use it.
+  hipMemPool_t pool = nullptr;
+  hipStream_t load_st[kLoadStreams] = {};
   // Serving sweeps every job in one part (launch_eval): the part count changes the rounding of a
   // job's sums, and a job's result must not depend on the other jobs of its steps.
   int sweep_order = 0;
@@ -281,7 +288,7 @@ NormSet* get_norm(mipwa_server* S, const ModelHost& mh, hipStream_t st, std::str
   ns->key = key;
   EffTable none;
   rc = load_points(mh, S->fp64, 1, S->n12.data(), S->n13.data(), S->nw.data(), nullptr, (long long)S->n12.size(),
-                   none, st, ns->ps, err);
+                   none, st, ns->ps, err, S->pool, S->stream);
   if (rc) return nullptr;
   ns->ps.cache.release();
   const size_t real = S->fp64 ? 8 : 4;
@@ -330,14 +337,11 @@ void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
 
 static void serve_worker(mipwa_server* S, SJob* J) {
   (void)hipSetDevice(S->device);
-  hipStream_t st = nullptr;
-  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-    finish_job(S, J, MIPWA_E_HIP, "stream creation failed");
-    return;
-  }
+  hipStream_t st = S->load_st[J->id % kLoadStreams];
   std::string err;
   EffTable none;
-  int rc = load_points(J->mh, S->fp64, 0, J->s12.data(), J->s13.data(), nullptr, nullptr, J->n, none, st, J->ev, err);
+  int rc = load_points(J->mh, S->fp64, 0, J->s12.data(), J->s13.data(), nullptr, nullptr, J->n, none, st, J->ev, err,
+                       S->pool, S->stream);
   J->s12 = std::vector<double>();
   J->s13 = std::vector<double>();
   NormSet* ns = nullptr;
@@ -361,12 +365,16 @@ static void serve_worker(mipwa_server* S, SJob* J) {
       cst[ni + i] = 1.0 / J->mh.th_d[i];
     }
     std::copy(J->mh.h.begin(), J->mh.h.end(), cst.begin() + 2 * ni);
-    if (J->mh.upload_res64(J->theta0.data(), J->d_tab) != MIPWA_OK ||
-        J->d_rec.alloc((size_t)(J->nb_d + J->nb_q) * J->rs * 8) ||
-        J->d_grec.alloc((size_t)(J->G_d + J->G_n) * J->rs * 8) ||
-        J->d_consts.alloc(cst.size() * 8) ||
-        J->d_ncache.alloc((size_t)std::max(J->mh.R, 1) * 2 * ns->ps.n * real) ||
-        J->d_mom.alloc((size_t)std::max(ns->ps.n_cells, 1) * qform_dim(J->mh.R) * qform_dim(J->mh.R) * 16)) {
+    // the job's memory is freed after the server's steps; the loading scratch after the load
+    hipMemPool_t pl = S->pool;
+    if (J->d_tab.alloc_from((size_t)kResWords * std::max(J->mh.R, 1) * 8, pl, st, st) ||
+        J->mh.upload_res64(J->theta0.data(), J->d_tab, st) != MIPWA_OK ||
+        J->d_rec.alloc_from((size_t)(J->nb_d + J->nb_q) * J->rs * 8, pl, st, S->stream) ||
+        J->d_grec.alloc_from((size_t)(J->G_d + J->G_n) * J->rs * 8, pl, st, S->stream) ||
+        J->d_consts.alloc_from(cst.size() * 8, pl, st, S->stream) ||
+        J->d_ncache.alloc_from((size_t)std::max(J->mh.R, 1) * 2 * ns->ps.n * real, pl, st, st) ||
+        J->d_mom.alloc_from((size_t)std::max(ns->ps.n_cells, 1) * qform_dim(J->mh.R) * qform_dim(J->mh.R) * 16, pl,
+                            st, S->stream)) {
       rc = MIPWA_E_NOMEM;
       err = "device allocation for a job failed";
     } else {
@@ -378,7 +386,7 @@ static void serve_worker(mipwa_server* S, SJob* J) {
       pts.tiles = ns->ps.tiles.as<Tile>();
       pts.n_tiles = ns->ps.n_tiles;
       pts.kind = 1;
-      if (hipMemcpy(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      if (hipMemcpyAsync(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
           launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
           launch_cache(S->fp64, J->mh.R, &sgn, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
           launch_moments(S->fp64, J->mh.R, &pts, ns->ps.cells.as<Tile>(), ns->ps.n_cells, J->d_mom.as<double>(),
@@ -391,7 +399,6 @@ static void serve_worker(mipwa_server* S, SJob* J) {
     J->d_tab.release();
     J->d_ncache.release();
   }
-  (void)hipStreamDestroy(st);
   if (rc) {
     finish_job(S, J, rc, err);
     return;
@@ -813,6 +820,20 @@ void sched_loop(mipwa_server* S) {
 
 }  // namespace
 
+// Streams, events and the memory pool of a server (any of them may be missing): every stream is
+// drained first, so no freed block is still in use when the pool is destroyed.
+static void release_device_objects(mipwa_server* S) {
+  for (hipStream_t st : S->load_st)
+    if (st) (void)hipStreamSynchronize(st);
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  for (hipEvent_t e : S->ev_step)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t st : S->load_st)
+    if (st) (void)hipStreamDestroy(st);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  if (S->pool) (void)hipMemPoolDestroy(S->pool);
+}
+
 extern "C" {
 
 int mipwa_server_create(int device, int precision, size_t budget, mipwa_server** out) {
@@ -828,11 +849,20 @@ int mipwa_server_create(int device, int precision, size_t budget, mipwa_server**
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)64 << 30;
   S->budget = budget ? budget : (size_t)(0.8 * (double)free_b);
-  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreate(&S->ev_step[0]) != hipSuccess || hipEventCreate(&S->ev_step[1]) != hipSuccess) {
-    for (hipEvent_t e : S->ev_step)
-      if (e) (void)hipEventDestroy(e);
-    if (S->stream) (void)hipStreamDestroy(S->stream);
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
+  uint64_t keep = UINT64_MAX;  // freed memory stays in the pool until the server is destroyed
+  bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreate(&S->ev_step[0]) == hipSuccess && hipEventCreate(&S->ev_step[1]) == hipSuccess &&
+            hipMemPoolCreate(&S->pool, &props) == hipSuccess &&
+            hipMemPoolSetAttribute(S->pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess;
+  for (int i = 0; ok && i < kLoadStreams; ++i)
+    ok = hipStreamCreateWithFlags(&S->load_st[i], hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    release_device_objects(S);
     delete S;
     return MIPWA_E_HIP;
   }
@@ -844,9 +874,7 @@ int mipwa_server_create(int device, int precision, size_t budget, mipwa_server**
         hipHostGetDevicePointer((void**)&B.h_res_dev, B.h_res.p, 0) != hipSuccess ||
         B.h_seq.alloc(kSeqBytes0, true) != hipSuccess ||
         hipHostGetDevicePointer((void**)&B.h_seq_dev, B.h_seq.p, 0) != hipSuccess) {
-      for (hipEvent_t e : S->ev_step)
-        if (e) (void)hipEventDestroy(e);
-      (void)hipStreamDestroy(S->stream);
+      release_device_objects(S);
       delete S;
       return MIPWA_E_NOMEM;
     }
@@ -1039,12 +1067,10 @@ void mipwa_server_destroy(mipwa_server* S) {
         "and launch %.3f s, waiting for results %.3f s, results to the jobs %.3f s, admission and joins %.3f s",
         S->steps, S->n_overlapped, S->t_idle, S->t_window, S->t_stage, S->t_gpu, S->t_wake, S->t_admit);
   (void)hipSetDevice(S->device);
-  (void)hipStreamSynchronize(S->stream);
+  // the jobs' and sets' memory goes back to the pool after the last step; then the pool goes
   S->jobs.clear();
   S->norms.clear();
-  for (hipEvent_t e : S->ev_step)
-    if (e) (void)hipEventDestroy(e);
-  (void)hipStreamDestroy(S->stream);
+  release_device_objects(S);
   delete S;
 }
 
