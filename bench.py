@@ -267,11 +267,12 @@ def small_fit_vs_oracle():
             "status": res.status}
 
 
-def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
+def serving(n_jobs, precision, rate_factor=0.8, log_every=32, borrow=True):
     """Toy-fit serving: n_jobs fits (event counts log-uniform in [1e4, 5e6], knots in {20,30,40,50},
     rho(770)+f2(1270), shapes fixed) against one shared 2M-point normalisation sample.  Run 1 submits
     every job at t=0 (capacity); run 2 submits them at Poisson arrival times with rate
-    rate_factor x capacity and reports fits/s and p50/p99 time-to-fit."""
+    rate_factor x capacity and reports fits/s and p50/p99 time-to-fit.  borrow: the jobs' event arrays
+    are lent to the server (read when each job loads) instead of copied at submission."""
     import synth
     from paper_1703_03284_amd import FP64, Server, context_for
     wl = synth.C1
@@ -303,7 +304,8 @@ def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
                 delay = arrivals[i] - (time.perf_counter() - start)
                 if delay > 0:
                     time.sleep(delay)
-            ids.append(srv.submit(d, kn, wl.resonances, s12, s13, th0, tol_edm=1e-4))
+            ids.append(srv.submit(d, kn, wl.resonances, s12, s13, th0, tol_edm=1e-4, copy=not borrow))
+        t_submit = time.perf_counter() - start
         res = []
         for k, j in enumerate(ids):
             res.append(srv.wait(j))
@@ -314,6 +316,8 @@ def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
         srv.close()
         n_ok = sum(1 for r in res if r["status"] == 0)
         n_noconv = sum(1 for r in res if r["status"] == -6)
+        log(f"[bench] serving: submissions took {t_submit:.3f}s of the run's {wall:.3f}s")
+        st["submission_s"] = t_submit
         return wall, st, (n_ok, n_noconv), res
 
     wall0, st0, ok0, _ = run(None)
@@ -329,6 +333,7 @@ def serving(n_jobs, precision, rate_factor=0.8, log_every=32):
             "mean_batch": st1["mean_batch"], "steps": st1["steps"], "peak_bytes": st1["peak_bytes"],
             "capacity_device_busy": st0["device_busy"], "capacity_step_device_us": 1e6 * st0["step_device_s"],
             "capacity_mean_batch": st0["mean_batch"], "capacity_steps": st0["steps"],
+            "capacity_submission_s": st0["submission_s"], "submission": "borrowed" if borrow else "copied",
             "device_busy": st1["device_busy"], "step_device_us": 1e6 * st1["step_device_s"],
             "converged": ok1[0], "not_converged": ok1[1], "tol_edm": 1e-4,
             "mean_evals_per_fit": float(np.mean([r.get("n_eval", 0) for r in res1])),

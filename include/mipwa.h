@@ -300,6 +300,13 @@ int mipwa_server_set_norm(mipwa_server* s, const double* s12, const double* s13,
 int mipwa_server_submit(mipwa_server* s, const mipwa_model* model, const double* s12, const double* s13, int64_t n,
                         const double* theta0, const unsigned char* fixed, const mipwa_fit_opts* opts,
                         int64_t* job_id);
+/* As mipwa_server_submit, without copying the events: the server reads s12 and s13 (host memory, not
+ * pinned) when the job is admitted and loaded, so the caller keeps both arrays valid and unchanged
+ * until mipwa_server_poll or mipwa_server_wait has returned the job's final status (or the server is
+ * destroyed).  Submitting many large jobs at once then costs no host copy in the caller's thread. */
+int mipwa_server_submit_borrowed(mipwa_server* s, const mipwa_model* model, const double* s12, const double* s13,
+                                 int64_t n, const double* theta0, const unsigned char* fixed,
+                                 const mipwa_fit_opts* opts, int64_t* job_id);
 /* Result of a job: MIPWA_E_BUSY while queued or running, MIPWA_E_CANCELLED, otherwise the fit status
  * (MIPWA_OK or MIPWA_E_NOCONV) with theta_out (P doubles, nullable), info (nullable) and the
  * time-to-fit in seconds (nullable) filled in; another negative code if loading or fitting failed. */

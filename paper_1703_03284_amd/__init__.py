@@ -282,6 +282,7 @@ class Server:
             raise MipwaError(rc, "mipwa_server_create")
         self._h = h
         self._models = {}
+        self._borrowed = {}  # job id -> the event arrays the server reads until the job's final result
 
     def _check(self, rc, what, ok=(0,)):
         if rc not in ok:
@@ -294,17 +295,22 @@ class Server:
         self._check(self._lib.mipwa_server_set_norm(self._h, L.dptr(s12), L.dptr(s13), L.dptr(w), len(s12)), "set_norm")
 
     def submit(self, decay, knots, resonances, s12, s13, theta0, fixed=None, tol_edm=1e-4, max_iter=1000,
-               hessian=False):
+               hessian=False, copy=True):
+        """Queue a fit.  copy=False lends the event arrays to the server instead of copying them
+        (mipwa_server_submit_borrowed): they are held here until the job's final result is read."""
         mh = _ModelHolder(decay.M, decay.m1, decay.m2, decay.m3, decay.rD, knots,
                           [Resonance(r.spin, r.mass, r.width, r.radius) for r in resonances])
         s12, s13, th = _f64(s12), _f64(s13), _f64(theta0)
         fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
         opts = L.FitOptsC(float(tol_edm), int(max_iter), int(bool(hessian)))
         jid = C.c_longlong()
-        self._check(self._lib.mipwa_server_submit(
-            self._h, C.byref(mh.c), L.dptr(s12), L.dptr(s13), len(s12), L.dptr(th),
-            None if fx is None else fx.ctypes.data_as(C.POINTER(C.c_ubyte)), C.byref(opts), C.byref(jid)), "submit")
+        fn = self._lib.mipwa_server_submit if copy else self._lib.mipwa_server_submit_borrowed
+        self._check(fn(self._h, C.byref(mh.c), L.dptr(s12), L.dptr(s13), len(s12), L.dptr(th),
+                       None if fx is None else fx.ctypes.data_as(C.POINTER(C.c_ubyte)), C.byref(opts),
+                       C.byref(jid)), "submit")
         self._models[jid.value] = len(th)
+        if not copy:
+            self._borrowed[jid.value] = (s12, s13)
         return jid.value
 
     def _result(self, fn, jid, *extra):
@@ -315,6 +321,7 @@ class Server:
         rc = fn(self._h, jid, *extra, L.dptr(th), C.byref(info), C.byref(lat))
         if rc == -8:
             return None
+        self._borrowed.pop(jid, None)  # final: the server no longer reads the job's events
         self._check(rc, "result", ok=(0, -6, -7))
         if rc == -7:
             return {"status": rc}
@@ -339,6 +346,7 @@ class Server:
         if getattr(self, "_h", None):
             self._lib.mipwa_server_destroy(self._h)
             self._h = None
+            self._borrowed = {}
 
     def __del__(self):
         try:

@@ -74,6 +74,8 @@ SIGNATURES = {
     "mipwa_server_set_norm": (C.c_int, [_P, _D, _D, _D, _I64]),
     "mipwa_server_submit": (C.c_int, [_P, C.POINTER(ModelC), _D, _D, _I64, _D, C.POINTER(C.c_ubyte),
                                       C.POINTER(FitOptsC), C.POINTER(_I64)]),
+    "mipwa_server_submit_borrowed": (C.c_int, [_P, C.POINTER(ModelC), _D, _D, _I64, _D, C.POINTER(C.c_ubyte),
+                                               C.POINTER(FitOptsC), C.POINTER(_I64)]),
     "mipwa_server_poll": (C.c_int, [_P, _I64, _D, C.POINTER(FitInfoC), _D]),
     "mipwa_server_wait": (C.c_int, [_P, _I64, C.c_double, _D, C.POINTER(FitInfoC), _D]),
     "mipwa_server_cancel": (C.c_int, [_P, _I64]),

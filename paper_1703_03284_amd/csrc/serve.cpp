@@ -57,6 +57,32 @@ constexpr int kLoadStreams = 4;                    // streams the jobs' loads ar
 // server may still hold one of its numbers.
 std::atomic<unsigned long long> g_step_seq{0};
 
+// The server's own copy of a job's events (the caller may free its arrays once submit returns), s12
+// then s13 in one block, left uninitialised until the copy.  Copying into freshly allocated memory
+// is bound by first-touch page faults, which proceed in parallel: large submissions are copied by
+// several threads.  (Huge pages made these copies faster but the loads' uploads from them slower.)
+double* alloc_events(long long n) { return new (std::nothrow) double[(size_t)2 * n]; }
+
+void copy_events(double* d12, double* d13, const double* s12, const double* s13, long long n) {
+  constexpr long long kPerThread = 1 << 20;  // events (16 MB of both coordinates)
+  const int T = (int)std::min<long long>(8, std::max<long long>(1, n / kPerThread));
+  auto part = [&](int t) {
+    const long long a = n * t / T, b = n * (t + 1) / T;
+    std::memcpy(d12 + a, s12 + a, (size_t)(b - a) * sizeof(double));
+    std::memcpy(d13 + a, s13 + a, (size_t)(b - a) * sizeof(double));
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) {
+    try {
+      th.emplace_back(part, t);
+    } catch (...) {
+      part(t);  // no thread to spare: this part on the caller's thread
+    }
+  }
+  part(0);
+  for (auto& x : th) x.join();
+}
+
 // blocks of a job's event segment: about kServeTilesPerWave tiles per wave
 int seg_blocks(int n_tiles) {
   const int per_block = kServeTilesPerWave * kServeWaves;
@@ -64,13 +90,25 @@ int seg_blocks(int n_tiles) {
   return std::min(std::max(b, 1), kMaxSegBlocks);
 }
 
+// Per-cell moments of a normalisation set's points at one set of resonance shapes: the normalisation
+// integral as a quadratic form.  The first job that needs them forms them; every job with the same
+// knots and shapes then uses the same buffer (the moments are the same numbers whichever job forms
+// them, so a job's results do not depend on which one did).
+struct Moments {
+  std::mutex m;  // held while the moments are formed
+  bool ready = false;
+  DevBuf d;
+};
+
 // The shared normalisation sample sorted for one knot grid: local spline coordinates, weights and
-// tiles.  The resonance amplitudes depend on each job's shapes and live with the job.
+// tiles, and its moments for each set of resonance shapes the jobs have asked for.
 struct NormSet {
   std::vector<double> key;  // kinematics and knots
   PointSet ps;              // no resonance cache of its own
   int nb = 0;
   size_t bytes = 0;
+  std::mutex mom_mu;        // the map below
+  std::map<std::vector<double>, std::unique_ptr<Moments>> moments;  // by resonance constants
 };
 
 enum JobState { QUEUED, LOADING, ACTIVE, FINISHED };
@@ -78,7 +116,9 @@ enum JobState { QUEUED, LOADING, ACTIVE, FINISHED };
 struct SJob {
   int64_t id = 0;
   ModelHost mh;
-  std::vector<double> s12, s13;
+  std::unique_ptr<double[]> ev_host;  // the server's copy of the events (s12 then s13), until loaded
+  const double* ev12 = nullptr;       // the events to load: the copy, or the caller's borrowed arrays
+  const double* ev13 = nullptr;
   long long n = 0;
   std::vector<double> theta0;
   std::vector<unsigned char> fixed;
@@ -89,9 +129,7 @@ struct SJob {
   NormSet* norm = nullptr;
   int nb_d = 0, G_d = 0, G_n = 0, rs = 0;
   DevBuf d_rec, d_grec, d_consts, d_tab;
-  DevBuf d_ncache;  // resonance amplitudes of the shared normalisation points at this job's shapes
-                    // (only while loading: the moments below are formed from them)
-  DevBuf d_mom;     // per-cell moments of the normalisation points: I as a quadratic form
+  const void* mom = nullptr;  // per-cell moments of the normalisation points at this job's shapes
   int nb_q = 0;     // blocks of the job's normalisation (cell) segment
   size_t bytes = 0;
   JobState state = QUEUED;
@@ -112,6 +150,8 @@ struct SJob {
   std::mutex m;
   std::condition_variable cv;
   FitOut result;
+  int load_slot = -1;               // the loader stream handed to this job (guarded by the server's load_mu)
+  std::condition_variable load_cv;  // signalled when it is handed one, or the server stops
 };
 
 std::vector<double> norm_key(const ModelHost& mh) {
@@ -170,7 +210,12 @@ struct mipwa_server {
   // stalling every other job's loads and the steps' launches) nor returns memory to the driver.
   // A job's memory is freed in the order of `stream`, after every step that may use it.
   hipMemPool_t pool = nullptr;
+  // Loads run one per loader stream at a time, in about the order jobs are admitted: many loads at
+  // once (each uploading its events from pageable host memory) slow every one of them down.
   hipStream_t load_st[kLoadStreams] = {};
+  std::mutex load_mu;                 // the two members below and the jobs' load_slot
+  bool load_busy[kLoadStreams] = {};
+  std::deque<SJob*> load_wait;        // jobs waiting for a loader stream, first come first served
   // Serving sweeps every job in one part (launch_eval): the part count changes the rounding of a
   // job's sums, and a job's result must not depend on the other jobs of its steps.
   int sweep_order = 0;
@@ -310,8 +355,6 @@ void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
   J->d_rec.release();
   J->d_grec.release();
   J->d_consts.release();
-  J->d_ncache.release();
-  J->d_mom.release();
   std::lock_guard<std::mutex> lk(S->mu);
   if (J->state == ACTIVE) S->n_active -= 1;
   if (J->req) {
@@ -337,13 +380,33 @@ void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
 
 static void serve_worker(mipwa_server* S, SJob* J) {
   (void)hipSetDevice(S->device);
-  hipStream_t st = S->load_st[J->id % kLoadStreams];
+  int slot = -1;
+  {
+    std::unique_lock<std::mutex> g(S->load_mu);
+    for (int i = 0; i < kLoadStreams && S->load_wait.empty(); ++i)
+      if (!S->load_busy[i]) {
+        slot = i;
+        S->load_busy[i] = true;
+        break;
+      }
+    if (slot < 0) {
+      S->load_wait.push_back(J);
+      J->load_cv.wait(g, [&] { return J->load_slot >= 0 || S->stop.load(); });
+      slot = J->load_slot;
+      if (slot < 0) S->load_wait.erase(std::find(S->load_wait.begin(), S->load_wait.end(), J));
+    }
+  }
+  if (slot < 0) {
+    finish_job(S, J, MIPWA_E_CANCELLED, "the server is shutting down");
+    return;
+  }
+  hipStream_t st = S->load_st[slot];
   std::string err;
   EffTable none;
-  int rc = load_points(J->mh, S->fp64, 0, J->s12.data(), J->s13.data(), nullptr, nullptr, J->n, none, st, J->ev, err,
+  int rc = load_points(J->mh, S->fp64, 0, J->ev12, J->ev13, nullptr, nullptr, J->n, none, st, J->ev, err,
                        S->pool, S->stream);
-  J->s12 = std::vector<double>();
-  J->s13 = std::vector<double>();
+  J->ev_host.reset();
+  J->ev12 = J->ev13 = nullptr;
   NormSet* ns = nullptr;
   if (!rc) ns = get_norm(S, J->mh, st, err, rc);
   if (!rc) {
@@ -371,33 +434,78 @@ static void serve_worker(mipwa_server* S, SJob* J) {
         J->mh.upload_res64(J->theta0.data(), J->d_tab, st) != MIPWA_OK ||
         J->d_rec.alloc_from((size_t)(J->nb_d + J->nb_q) * J->rs * 8, pl, st, S->stream) ||
         J->d_grec.alloc_from((size_t)(J->G_d + J->G_n) * J->rs * 8, pl, st, S->stream) ||
-        J->d_consts.alloc_from(cst.size() * 8, pl, st, S->stream) ||
-        J->d_ncache.alloc_from((size_t)std::max(J->mh.R, 1) * 2 * ns->ps.n * real, pl, st, st) ||
-        J->d_mom.alloc_from((size_t)std::max(ns->ps.n_cells, 1) * qform_dim(J->mh.R) * qform_dim(J->mh.R) * 16, pl,
-                            st, S->stream)) {
+        J->d_consts.alloc_from(cst.size() * 8, pl, st, S->stream)) {
       rc = MIPWA_E_NOMEM;
       err = "device allocation for a job failed";
+    } else if (hipMemcpyAsync(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+               launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess) {
+      rc = MIPWA_E_HIP;
+      err = "loading a job failed";
     } else {
-      sgn.cache = J->d_ncache.p;
-      // the full point segment of the normalisation set for the moment pass
-      Segment pts = sgn;
-      pts.tt = ns->ps.tt.p;
-      pts.w = ns->ps.w.p;
-      pts.tiles = ns->ps.tiles.as<Tile>();
-      pts.n_tiles = ns->ps.n_tiles;
-      pts.kind = 1;
-      if (hipMemcpyAsync(J->d_consts.p, cst.data(), cst.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
-          launch_cache(S->fp64, J->mh.R, &sg, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
-          launch_cache(S->fp64, J->mh.R, &sgn, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
-          launch_moments(S->fp64, J->mh.R, &pts, ns->ps.cells.as<Tile>(), ns->ps.n_cells, J->d_mom.as<double>(),
-                         st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess) {
+      // the moments at the job's shapes: found, or formed here from the normalisation points'
+      // resonance amplitudes (scratch of this load)
+      std::vector<double> rkey((size_t)kResWords * std::max(J->mh.R, 1) + 1, 0.0);
+      rkey[0] = J->mh.R;
+      J->mh.res_table(J->theta0.data(), rkey.data() + 1);
+      Moments* mo = nullptr;
+      {
+        std::lock_guard<std::mutex> g(ns->mom_mu);
+        auto& e = ns->moments[rkey];
+        if (!e) e = std::make_unique<Moments>();
+        mo = e.get();
+      }
+      std::lock_guard<std::mutex> g(mo->m);
+      if (!mo->ready) {
+        const size_t mom_bytes =
+            (size_t)std::max(ns->ps.n_cells, 1) * qform_dim(J->mh.R) * qform_dim(J->mh.R) * 16;
+        DevBuf ncache;
+        if (ncache.alloc_from((size_t)std::max(J->mh.R, 1) * 2 * ns->ps.n * real, pl, st, st) ||
+            mo->d.alloc_from(mom_bytes, pl, st, S->stream)) {
+          rc = MIPWA_E_NOMEM;
+          err = "device allocation for the normalisation moments failed";
+        } else {
+          sgn.cache = ncache.p;
+          // the full point segment of the normalisation set for the moment pass
+          Segment pts = sgn;
+          pts.tt = ns->ps.tt.p;
+          pts.w = ns->ps.w.p;
+          pts.tiles = ns->ps.tiles.as<Tile>();
+          pts.n_tiles = ns->ps.n_tiles;
+          pts.kind = 1;
+          if (launch_cache(S->fp64, J->mh.R, &sgn, J->d_tab.as<double>(), J->mh.kin64, st) != hipSuccess ||
+              launch_moments(S->fp64, J->mh.R, &pts, ns->ps.cells.as<Tile>(), ns->ps.n_cells, mo->d.as<double>(),
+                             st) != hipSuccess ||
+              hipStreamSynchronize(st) != hipSuccess) {
+            rc = MIPWA_E_HIP;
+            err = "forming the normalisation moments failed";
+          } else {
+            mo->ready = true;
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->used += mom_bytes;
+            S->peak = std::max(S->peak, S->used);
+          }
+        }
+        if (!mo->ready) mo->d.release();
+      }
+      if (!rc && hipStreamSynchronize(st) != hipSuccess) {
         rc = MIPWA_E_HIP;
         err = "loading a job failed";
       }
+      J->mom = mo->ready ? mo->d.p : nullptr;
     }
     J->d_tab.release();
-    J->d_ncache.release();
+  }
+  {
+    // the stream goes to the longest-waiting job, else back to the free ones
+    std::lock_guard<std::mutex> g(S->load_mu);
+    if (!S->load_wait.empty()) {
+      SJob* next = S->load_wait.front();
+      S->load_wait.pop_front();
+      next->load_slot = slot;
+      next->load_cv.notify_one();
+    } else {
+      S->load_busy[slot] = false;
+    }
   }
   if (rc) {
     finish_job(S, J, rc, err);
@@ -592,7 +700,7 @@ int launch_step(mipwa_server* S, Step& st) {
           s.kind = 2;
           s.tiles = ps[k]->cells.as<Tile>();
           s.n_tiles = ps[k]->n_cells;
-          s.cache = J->d_mom.p;
+          s.cache = J->mom;
         }
         s.nint = J->mh.N - 1;
         s.rs = J->rs;
@@ -896,9 +1004,9 @@ int mipwa_server_set_norm(mipwa_server* S, const double* s12, const double* s13,
   return MIPWA_OK;
 }
 
-int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double* s12, const double* s13, int64_t n,
-                        const double* theta0, const unsigned char* fixed, const mipwa_fit_opts* opts,
-                        int64_t* job_id) {
+static int submit_job(mipwa_server* S, const mipwa_model* model, const double* s12, const double* s13, int64_t n,
+                      const double* theta0, const unsigned char* fixed, const mipwa_fit_opts* opts, int64_t* job_id,
+                      bool borrow) {
   if (!S) return MIPWA_E_INVAL;
   size_t n_norm = 0;
   {
@@ -923,8 +1031,16 @@ int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double*
   }
   for (int p = 2 * N + 2 * R; p < P; ++p)
     if (!J->fixed[p]) return S->fail(MIPWA_E_INVAL, "serving jobs keep masses and widths fixed");
-  J->s12.assign(s12, s12 + n);
-  J->s13.assign(s13, s13 + n);
+  if (borrow) {
+    J->ev12 = s12;
+    J->ev13 = s13;
+  } else {
+    J->ev_host.reset(alloc_events(n));
+    if (!J->ev_host) return S->fail(MIPWA_E_NOMEM, "no host memory for the job's events");
+    copy_events(J->ev_host.get(), J->ev_host.get() + n, s12, s13, n);
+    J->ev12 = J->ev_host.get();
+    J->ev13 = J->ev_host.get() + n;
+  }
   J->n = n;
   J->theta0.assign(theta0, theta0 + P);
   J->tol = opts && opts->tol_edm > 0 ? opts->tol_edm : 1e-4;
@@ -947,6 +1063,18 @@ int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double*
   S->jobs[J->id] = std::move(J);
   S->cv_sched.notify_all();
   return MIPWA_OK;
+}
+
+int mipwa_server_submit(mipwa_server* S, const mipwa_model* model, const double* s12, const double* s13, int64_t n,
+                        const double* theta0, const unsigned char* fixed, const mipwa_fit_opts* opts,
+                        int64_t* job_id) {
+  return submit_job(S, model, s12, s13, n, theta0, fixed, opts, job_id, false);
+}
+
+int mipwa_server_submit_borrowed(mipwa_server* S, const mipwa_model* model, const double* s12, const double* s13,
+                                 int64_t n, const double* theta0, const unsigned char* fixed,
+                                 const mipwa_fit_opts* opts, int64_t* job_id) {
+  return submit_job(S, model, s12, s13, n, theta0, fixed, opts, job_id, true);
 }
 
 namespace {
@@ -1059,6 +1187,10 @@ void mipwa_server_destroy(mipwa_server* S) {
       wake(kv.second.get());
     }
     S->cv_sched.notify_all();
+  }
+  {
+    std::lock_guard<std::mutex> g(S->load_mu);  // jobs waiting for a loader stream give up
+    for (SJob* J : S->load_wait) J->load_cv.notify_one();
   }
   if (S->sched.joinable()) S->sched.join();
   for (auto& kv : S->jobs)

@@ -45,6 +45,28 @@ def _submit(srv, job, **kw):
     return srv.submit(wl.decay, kn, wl.resonances, s12, s13, start, **kw)
 
 
+def test_borrowed_events_give_the_copied_result(norm, jobs):
+    # the same jobs submitted with copies and with lent arrays (read by the server when they load):
+    # bitwise the same fits, the lent arrays untouched, and released once the final result is read
+    with _server(norm) as s1:
+        ref = [s1.wait(_submit(s1, jobs[k])) for k in ("A", "B")]
+    lent = {k: (jobs[k][3].copy(), jobs[k][4].copy()) for k in ("A", "B")}
+    with _server(norm) as s2:
+        ids = []
+        for k in ("A", "B"):
+            kn, _, start, _, _ = jobs[k]
+            wl = synth.C1
+            ids.append(s2.submit(wl.decay, kn, wl.resonances, lent[k][0], lent[k][1], start, copy=False))
+        assert set(s2._borrowed) == set(ids)
+        got = [s2.wait(i) for i in ids]
+        assert s2._borrowed == {}
+    for r, g in zip(ref, got):
+        assert r["status"] == 0 and g["status"] == 0
+        assert np.array_equal(r["theta"], g["theta"]) and r["nll"] == g["nll"] and r["n_eval"] == g["n_eval"]
+    for k in ("A", "B"):
+        assert np.array_equal(lent[k][0], jobs[k][3]) and np.array_equal(lent[k][1], jobs[k][4])
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_result_alone_equals_result_in_the_mix(norm, jobs, precision):
     with _server(norm, precision) as s1:
