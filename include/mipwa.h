@@ -282,7 +282,7 @@ typedef struct {
   int64_t peak_bytes;  /* largest admitted device footprint (events, scratch, normalisation sets) */
   int64_t steps;       /* batched launches so far */
   double mean_batch;   /* mean number of jobs per launch */
-  double step_device_s; /* mean device time of a step (HIP events around every 16th step's kernels) */
+  double step_device_s; /* mean device time of a step (HIP events around every 17th step's kernels) */
   double device_busy;  /* step_device_s x steps / (last completion - first submission) */
 } mipwa_serve_stats;
 

@@ -47,7 +47,8 @@ constexpr int kServeWaves = 4;
 constexpr int kServeTilesPerWave = 8;
 constexpr int kMaxSegBlocks = 512;
 constexpr int kBatchWindowUs = 50;
-constexpr int kStepTimingPeriod = 16;
+// odd: consecutive steps alternate between two groups of jobs, so an even period would time one group only
+constexpr int kStepTimingPeriod = 17;
 constexpr size_t kBatchBytes0 = (size_t)4 << 20;   // initial step descriptor buffer (host and device)
 constexpr size_t kResultBytes0 = (size_t)1 << 20;  // initial result buffer (mapped host memory)
 constexpr size_t kSeqBytes0 = (size_t)64 << 10;    // initial sequence words: 8192 jobs per step
@@ -133,6 +134,7 @@ struct SJob {
   int nb_q = 0;     // blocks of the job's normalisation (cell) segment
   size_t bytes = 0;
   JobState state = QUEUED;
+  bool retired = false;  // FINISHED and its memory returned: the worker thread is about to end
   int status = MIPWA_OK;
   std::atomic<bool> cancel{false};
   std::string err;
@@ -349,30 +351,34 @@ NormSet* get_norm(mipwa_server* S, const ModelHost& mh, hipStream_t st, std::str
 }
 
 void finish_job(mipwa_server* S, SJob* J, int status, const std::string& err) {
-  // no step uses the job's buffers any more; freeing device memory waits for the device, so it
-  // happens before the server's lock is taken
+  // the result first: no step uses the job any more, and returning its memory (below) takes a while
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (J->state == ACTIVE) S->n_active -= 1;
+    if (J->req) {
+      J->req = false;
+      S->n_req -= 1;
+    }
+    J->state = FINISHED;
+    J->status = status;
+    J->err = err;
+    J->t_done = Clock::now();
+    trace(S, "job %lld done: status %d, %d evaluations", (long long)J->id, status, J->result.n_eval);
+    if (status == MIPWA_OK || status == MIPWA_E_NOCONV) {
+      S->latencies.push_back(std::chrono::duration<double>(J->t_done - J->t_submit).count());
+      S->t_last_done = J->t_done;
+    }
+    S->cv_done.notify_all();
+  }
+  // then its device memory, back to the pool after the steps already queued, and its share of the budget
   J->ev = PointSet();
   J->d_rec.release();
   J->d_grec.release();
   J->d_consts.release();
   std::lock_guard<std::mutex> lk(S->mu);
-  if (J->state == ACTIVE) S->n_active -= 1;
-  if (J->req) {
-    J->req = false;
-    S->n_req -= 1;
-  }
-  J->state = FINISHED;
-  J->status = status;
-  J->err = err;
-  J->t_done = Clock::now();
-  trace(S, "job %lld done: status %d, %d evaluations", (long long)J->id, status, J->result.n_eval);
-  if (status == MIPWA_OK || status == MIPWA_E_NOCONV) {
-    S->latencies.push_back(std::chrono::duration<double>(J->t_done - J->t_submit).count());
-    S->t_last_done = J->t_done;
-  }
   S->used -= J->bytes;
   S->running -= 1;
-  S->cv_done.notify_all();
+  J->retired = true;  // the scheduler joins the worker (under the server's lock) only from here on
   S->cv_sched.notify_all();
 }
 
@@ -852,7 +858,7 @@ void sched_loop(mipwa_server* S) {
     const auto t_0 = Clock::now();
     admit(S);
     for (auto& kv : S->jobs)
-      if (kv.second->state == FINISHED && kv.second->worker.joinable()) kv.second->worker.join();
+      if (kv.second->retired && kv.second->worker.joinable()) kv.second->worker.join();
     S->t_admit += std::chrono::duration<double>(Clock::now() - t_0).count();
     auto admissible = [&] {
       if (S->queue.empty()) return false;
