@@ -100,6 +100,15 @@ struct ArgTable {
 // [sum] [2R: sum g conj(R_r)] [OTF: 2R sum g conj(dR_r/dm), 2R sum g conj(dR_r/dGamma)].
 __host__ __device__ inline int record_size(int nint, int R, bool otf) { return 8 * nint + 1 + 2 * R + (otf ? 4 * R : 0); }
 __host__ __device__ inline int table_words(int nint, int R) { return 8 * nint + 2 * R + kResWords * R; }
+// An FP32 table is followed by the rounding residues of the coefficients that set the amplitude's size,
+// [P_0 re, P_0 im, P_1 re, P_1 im of each interval | c_r re, im]: a coefficient is its FP32 word plus
+// its residue, which carries the FP64 value to about 2^-48 (a rounding of the coefficients alone would
+// act like a shift of theta by one FP32 ulp, coherent over every point).
+__host__ __device__ inline int table_lo_words(int nint, int R) { return 4 * nint + 2 * R; }
+// words of the table in the working precision
+__host__ __device__ inline int table_real_words(int nint, int R, bool fp64) {
+  return table_words(nint, R) + (fp64 ? 0 : table_lo_words(nint, R));
+}
 
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
 // resonance cache of a segment, computed in FP64 from res64 (device, kResWords x R FP64 constants) and

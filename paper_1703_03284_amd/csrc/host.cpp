@@ -203,6 +203,28 @@ void ModelHost::res_table(const double* theta, double* out) const {
   }
 }
 
+void ModelHost::eval_table(const double* theta, bool fp64, void* out) const {
+  const int nint = N - 1, tw = table_words(nint, R);
+  std::vector<double> tab(tw);
+  poly_table(theta, tab.data());
+  for (int r = 0; r < R; ++r) {
+    const double cm = theta[2 * N + 2 * r], ca = theta[2 * N + 2 * r + 1];
+    tab[8 * nint + 2 * r] = cm * std::cos(ca);
+    tab[8 * nint + 2 * r + 1] = cm * std::sin(ca);
+  }
+  res_table(theta, tab.data() + 8 * nint + 2 * R);
+  if (fp64) {
+    std::memcpy(out, tab.data(), (size_t)tw * sizeof(double));
+    return;
+  }
+  float* f = static_cast<float*>(out);
+  for (int i = 0; i < tw; ++i) f[i] = (float)tab[i];
+  float* lo = f + tw;
+  for (int j = 0; j < nint; ++j)
+    for (int m = 0; m < 4; ++m) lo[4 * j + m] = (float)(tab[8 * j + m] - (double)f[8 * j + m]);
+  for (int k = 0; k < 2 * R; ++k) lo[4 * nint + k] = (float)(tab[8 * nint + k] - (double)f[8 * nint + k]);
+}
+
 int ModelHost::upload_res64(const double* theta, DevBuf& d, hipStream_t st) const {
   std::vector<double> r((size_t)kResWords * std::max(R, 1), 0.0);
   res_table(theta, r.data());

@@ -230,11 +230,16 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   constexpr int IT = kTile / 64;
   const Real* __restrict__ cv = tab + 8 * sg.nint;
   const Real* __restrict__ res = cv + 2 * R;
-  Real cre[R1], cim[R1];
+  // FP32: the residues of P_0, P_1 and c_r follow the table
+  constexpr bool kLo = sizeof(Real) < sizeof(double);
+  const Real* __restrict__ lo = tab + table_words(sg.nint, R);
+  Real cre[R1], cim[R1], cre_lo[R1], cim_lo[R1];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     cre[r] = O::uniform(cv[2 * r]);
     cim[r] = O::uniform(cv[2 * r + 1]);
+    cre_lo[r] = kLo ? O::uniform(lo[4 * sg.nint + 2 * r]) : Real(0);
+    cim_lo[r] = kLo ? O::uniform(lo[4 * sg.nint + 2 * r + 1]) : Real(0);
   }
   const V2* __restrict__ tt = uniform_ptr((const V2*)sg.tt);
   const double2* __restrict__ ss = uniform_ptr((const double2*)sg.ss);
@@ -266,9 +271,11 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   for (int r = 0; r < 2 * R1; ++r) tgc[r] = thm[r] = thg[r] = Real(0);
 
   int cj12 = -1, cj13 = -1;
-  Real p12[8], p13[8];
+  Real p12[8], p13[8], e12[4], e13[4];  // e: residues of P_0, P_1 (FP32 tables)
 #pragma unroll
   for (int m = 0; m < 8; ++m) p12[m] = p13[m] = Real(0);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) e12[m] = e13[m] = Real(0);
   double* hb = bins;  // interval histogram of the part being swept
 
   auto flush = [&]() {
@@ -300,10 +307,18 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     Real ai = p12[1] + x12 * (p12[3] + x12 * (p12[5] + x12 * p12[7]));
     ar += p13[0] + x13 * (p13[2] + x13 * (p13[4] + x13 * p13[6]));
     ai += p13[1] + x13 * (p13[3] + x13 * (p13[5] + x13 * p13[7]));
+    if constexpr (kLo) {
+      ar += (e12[0] + x12 * e12[2]) + (e13[0] + x13 * e13[2]);
+      ai += (e12[1] + x12 * e12[3]) + (e13[1] + x13 * e13[3]);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       ar += cre[r] * rr[r] - cim[r] * ri[r];
       ai += cre[r] * ri[r] + cim[r] * rr[r];
+      if constexpr (kLo) {
+        ar += cre_lo[r] * rr[r] - cim_lo[r] * ri[r];
+        ai += cre_lo[r] * ri[r] + cim_lo[r] * rr[r];
+      }
     }
     const Real a2 = ar * ar + ai * ai;
     Real gr, gi;
@@ -362,6 +377,13 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
       for (int m = 0; m < 8; ++m) {
         p12[m] = O::uniform(tab[8 * cj12 + m]);
         p13[m] = O::uniform(tab[8 * cj13 + m]);
+      }
+      if constexpr (kLo) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          e12[m] = O::uniform(lo[4 * cj12 + m]);
+          e13[m] = O::uniform(lo[4 * cj13 + m]);
+        }
       }
     }
   };
@@ -587,6 +609,8 @@ __device__ void run_qform(const Segment& sg, const Real* tab, double* bins, doub
   const int c1 = (int)(sg.n_tiles * (gw + 1) / nw);
   const double* __restrict__ mom = (const double*)sg.cache;
   const Real* cv = tab + 8 * sg.nint;
+  constexpr bool kLo = sizeof(Real) < sizeof(double);
+  const Real* lo = tab + table_words(sg.nint, R);  // FP32: residues of P_0, P_1 and c_r
   double acc = 0.0, gre = 0.0, gim = 0.0;
   for (int c = c0; c < c1; ++c) {
     const Tile cell = sg.tiles[c];
@@ -602,6 +626,20 @@ __device__ void run_qform(const Segment& sg, const Real* tab, double* bins, doub
     for (int r = 0; r < R; ++r) {
       vr[8 + r] = (double)cv[2 * r];
       vi[8 + r] = (double)cv[2 * r + 1];
+    }
+    if constexpr (kLo) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        vr[m] += (double)lo[4 * cell.j12 + 2 * m];
+        vi[m] += (double)lo[4 * cell.j12 + 2 * m + 1];
+        vr[4 + m] += (double)lo[4 * cell.j13 + 2 * m];
+        vi[4 + m] += (double)lo[4 * cell.j13 + 2 * m + 1];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        vr[8 + r] += (double)lo[4 * sg.nint + 2 * r];
+        vi[8 + r] += (double)lo[4 * sg.nint + 2 * r + 1];
+      }
     }
     double yr = 0.0, yi = 0.0, ur = 0.0, ui = 0.0;
     if (lane < K) {
@@ -919,14 +957,15 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
   const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
   const int stride = 8 * max_nint;
   // LDS: [evaluation table | interval histograms, `parts` per wave | sets of scalars, `parts` per wave]
-  const int tw = (table_words(max_nint, R) * (int)sizeof(Real) + 7) / 8;
+  constexpr bool kF64 = sizeof(Real) == sizeof(double);
+  const int tw = (table_real_words(max_nint, R, kF64) * (int)sizeof(Real) + 7) / 8;
   double* tab_lds = lds;
   double* bins = lds + tw;
   double* scal = bins + parts * waves * stride;
   {
     const unsigned* src = sg.table ? (const unsigned*)sg.table : (const unsigned*)targ.w;
     unsigned* dst = (unsigned*)tab_lds;
-    const int words = table_words(sg.nint, R) * (int)sizeof(Real) / 4;
+    const int words = table_real_words(sg.nint, R, kF64) * (int)sizeof(Real) / 4;
     for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
   }
   for (int i = threadIdx.x; i < parts * waves * (stride + nsc); i += blockDim.x) bins[i] = 0.0;
@@ -1312,7 +1351,7 @@ hipError_t eval_impl2(int R, const Segment* segs, const int2* bs, const Job* job
                       hipEvent_t e1) {
   Kin<Real> k = *(const Kin<Real>*)kin;
   const int nsc = 1 + 2 * R + (OTF ? 4 * R : 0);
-  const int tw = (table_words(max_nint, R) * (int)sizeof(Real) + 7) / 8;
+  const int tw = (table_real_words(max_nint, R, sizeof(Real) == sizeof(double)) * (int)sizeof(Real) + 7) / 8;
   // as many parts as asked for whose histograms fit the 64 KiB a workgroup may take; one with shapes
   // floated (that sweep is bound by the vector ALU, not by reads the Infinity Cache could serve)
   if (OTF) parts = 1;

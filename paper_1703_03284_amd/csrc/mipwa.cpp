@@ -188,26 +188,13 @@ int mipwa_ctx::stage_params() {
   // wait until the previous upload has left the staging buffer (evaluations whose tables travel in
   // the kernel arguments upload nothing; mipwa_integrals waits for its own upload before returning)
   if (!use_arg) HIPCHK(hipEventSynchronize(ev_staged), "staging wait");
-  const int nint = mh.N - 1, R = mh.R;
-  std::vector<double> tab(table_words(nint, R));
-  mh.poly_table(theta.data(), tab.data());
-  for (int r = 0; r < R; ++r) {
-    const double cm = theta[2 * mh.N + 2 * r], ca = theta[2 * mh.N + 2 * r + 1];
-    tab[8 * nint + 2 * r] = cm * std::cos(ca);
-    tab[8 * nint + 2 * r + 1] = cm * std::sin(ca);
-  }
-  mh.res_table(theta.data(), tab.data() + 8 * nint + 2 * R);
+  const size_t tbytes = (size_t)table_real_words(mh.N - 1, mh.R, fp64) * (fp64 ? 8 : 4);
   char* hb = h_blob.as<char>();
-  if (fp64) {
-    std::memcpy(hb, tab.data(), tab.size() * sizeof(double));
-  } else {
-    float* f = reinterpret_cast<float*>(hb);
-    for (size_t i = 0; i < tab.size(); ++i) f[i] = (float)tab[i];
-  }
+  mh.eval_table(theta.data(), fp64, hb);
   std::memcpy(hb + tab64_off, theta.data(), mh.P * sizeof(double));
   if (use_arg) {
     char* a = reinterpret_cast<char*>(h_args.w);
-    std::memcpy(a, hb, tab.size() * (fp64 ? 8 : 4));
+    std::memcpy(a, hb, tbytes);
     std::memcpy(a + arg_theta_off, theta.data(), mh.P * sizeof(double));
   }
   return MIPWA_OK;
@@ -419,7 +406,7 @@ int mipwa_create(const mipwa_model* model, int precision, int device, mipwa_ctx*
   }
   const mipwa::ModelHost& mh = ctx->mh;
   const size_t real = ctx->fp64 ? 8 : 4;
-  const size_t tbytes = table_words(mh.N - 1, mh.R) * real;
+  const size_t tbytes = table_real_words(mh.N - 1, mh.R, ctx->fp64) * real;
   ctx->tab64_off = (tbytes + 255) / 256 * 256;
   ctx->upload_bytes = ctx->tab64_off + mh.P * sizeof(double);
   ctx->consts_off = ctx->upload16();  // the per-evaluation upload never reaches the constants

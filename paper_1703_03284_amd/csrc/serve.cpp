@@ -163,7 +163,7 @@ std::vector<double> norm_key(const ModelHost& mh) {
 }
 
 size_t staged_bytes(const ModelHost& mh, bool fp64, size_t* theta_off) {
-  const size_t t = table_words(mh.N - 1, mh.R) * (fp64 ? 8 : 4);
+  const size_t t = table_real_words(mh.N - 1, mh.R, fp64) * (fp64 ? 8 : 4);
   *theta_off = (t + 255) / 256 * 256;
   return *theta_off + (size_t)mh.P * 8;
 }
@@ -172,21 +172,7 @@ size_t staged_bytes(const ModelHost& mh, bool fp64, size_t* theta_off) {
 void stage(const ModelHost& mh, bool fp64, const double* theta, std::vector<char>& out) {
   size_t toff = 0;
   out.assign(staged_bytes(mh, fp64, &toff), 0);
-  const int nint = mh.N - 1, R = mh.R;
-  std::vector<double> tab(table_words(nint, R));
-  mh.poly_table(theta, tab.data());
-  for (int r = 0; r < R; ++r) {
-    const double cm = theta[2 * mh.N + 2 * r], ca = theta[2 * mh.N + 2 * r + 1];
-    tab[8 * nint + 2 * r] = cm * std::cos(ca);
-    tab[8 * nint + 2 * r + 1] = cm * std::sin(ca);
-  }
-  mh.res_table(theta, tab.data() + 8 * nint + 2 * R);
-  if (fp64) {
-    std::memcpy(out.data(), tab.data(), tab.size() * 8);
-  } else {
-    float* f = reinterpret_cast<float*>(out.data());
-    for (size_t i = 0; i < tab.size(); ++i) f[i] = (float)tab[i];
-  }
+  mh.eval_table(theta, fp64, out.data());
   std::memcpy(out.data() + toff, theta, (size_t)mh.P * 8);
 }
 
