@@ -203,7 +203,7 @@ void ModelHost::res_table(const double* theta, double* out) const {
   }
 }
 
-void ModelHost::eval_table(const double* theta, bool fp64, void* out) const {
+void ModelHost::eval_table(const double* theta, bool fp64, void* out, bool residues) const {
   const int nint = N - 1, tw = table_words(nint, R);
   std::vector<double> tab(tw);
   poly_table(theta, tab.data());
@@ -220,6 +220,10 @@ void ModelHost::eval_table(const double* theta, bool fp64, void* out) const {
   float* f = static_cast<float*>(out);
   for (int i = 0; i < tw; ++i) f[i] = (float)tab[i];
   float* lo = f + tw;
+  if (!residues) {
+    std::memset(lo, 0, (size_t)table_lo_words(nint, R) * sizeof(float));
+    return;
+  }
   for (int j = 0; j < nint; ++j)
     for (int m = 0; m < 4; ++m) lo[4 * j + m] = (float)(tab[8 * j + m] - (double)f[8 * j + m]);
   for (int k = 0; k < 2 * R; ++k) lo[4 * nint + k] = (float)(tab[8 * nint + k] - (double)f[8 * nint + k]);

@@ -132,8 +132,9 @@ struct ModelHost {
   // per-resonance constants (kResWords doubles each) at the given masses/widths in theta
   void res_table(const double* theta, double* out) const;
   // the evaluation table at theta in the working precision: table_real_words(N - 1, R, fp64) words
-  // (doubles, or floats followed by their residues) at out
-  void eval_table(const double* theta, bool fp64, void* out) const;
+  // (doubles, or floats followed by their residues; zeros in place of the residues when `residues` is
+  // false) at out
+  void eval_table(const double* theta, bool fp64, void* out, bool residues = true) const;
   // FP64 resonance constants at theta into a device buffer (synchronous; the copy is made in the
   // order of stream st when one is given, for memory allocated in that order)
   int upload_res64(const double* theta, DevBuf& d, hipStream_t st = nullptr) const;

@@ -230,8 +230,9 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   constexpr int IT = kTile / 64;
   const Real* __restrict__ cv = tab + 8 * sg.nint;
   const Real* __restrict__ res = cv + 2 * R;
-  // FP32: the residues of P_0, P_1 and c_r follow the table
-  constexpr bool kLo = sizeof(Real) < sizeof(double);
+  // FP32: the residues of P_0, P_1 and c_r follow the table (zeros when the host gives none); the
+  // floated-shape sweep, bound by the vector ALU, leaves them out
+  constexpr bool kLo = sizeof(Real) < sizeof(double) && !OTF;
   const Real* __restrict__ lo = tab + table_words(sg.nint, R);
   Real cre[R1], cim[R1], cre_lo[R1], cim_lo[R1];
 #pragma unroll
@@ -608,9 +609,9 @@ __device__ void run_qform(const Segment& sg, const Real* tab, double* bins, doub
   const int c0 = (int)(sg.n_tiles * gw / nw);
   const int c1 = (int)(sg.n_tiles * (gw + 1) / nw);
   const double* __restrict__ mom = (const double*)sg.cache;
+  // (the quadratic form is given tables without residues: the data sweep it pairs with must see the
+  // same coefficients, and its FP32 arithmetic would keep only part of them)
   const Real* cv = tab + 8 * sg.nint;
-  constexpr bool kLo = sizeof(Real) < sizeof(double);
-  const Real* lo = tab + table_words(sg.nint, R);  // FP32: residues of P_0, P_1 and c_r
   double acc = 0.0, gre = 0.0, gim = 0.0;
   for (int c = c0; c < c1; ++c) {
     const Tile cell = sg.tiles[c];
@@ -626,20 +627,6 @@ __device__ void run_qform(const Segment& sg, const Real* tab, double* bins, doub
     for (int r = 0; r < R; ++r) {
       vr[8 + r] = (double)cv[2 * r];
       vi[8 + r] = (double)cv[2 * r + 1];
-    }
-    if constexpr (kLo) {
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        vr[m] += (double)lo[4 * cell.j12 + 2 * m];
-        vi[m] += (double)lo[4 * cell.j12 + 2 * m + 1];
-        vr[4 + m] += (double)lo[4 * cell.j13 + 2 * m];
-        vi[4 + m] += (double)lo[4 * cell.j13 + 2 * m + 1];
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        vr[8 + r] += (double)lo[4 * sg.nint + 2 * r];
-        vi[8 + r] += (double)lo[4 * sg.nint + 2 * r + 1];
-      }
     }
     double yr = 0.0, yi = 0.0, ur = 0.0, ui = 0.0;
     if (lane < K) {

@@ -190,7 +190,10 @@ int mipwa_ctx::stage_params() {
   if (!use_arg) HIPCHK(hipEventSynchronize(ev_staged), "staging wait");
   const size_t tbytes = (size_t)table_real_words(mh.N - 1, mh.R, fp64) * (fp64 ? 8 : 4);
   char* hb = h_blob.as<char>();
-  mh.eval_table(theta.data(), fp64, hb);
+  // residues only where the data and the normalisation are both FP32 point sweeps (they keep the same
+  // part of them); the quadratic form's FP64 arithmetic would keep all of them, and a normalisation
+  // that sees the coefficients otherwise than the data term shifts the fit's minimum
+  mh.eval_table(theta.data(), fp64, hb, !use_qform());
   std::memcpy(hb + tab64_off, theta.data(), mh.P * sizeof(double));
   if (use_arg) {
     char* a = reinterpret_cast<char*>(h_args.w);

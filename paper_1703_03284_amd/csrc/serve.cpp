@@ -172,7 +172,9 @@ size_t staged_bytes(const ModelHost& mh, bool fp64, size_t* theta_off) {
 void stage(const ModelHost& mh, bool fp64, const double* theta, std::vector<char>& out) {
   size_t toff = 0;
   out.assign(staged_bytes(mh, fp64, &toff), 0);
-  mh.eval_table(theta, fp64, out.data());
+  // no residues: the normalisation is a quadratic form in FP64, the data a sweep in FP32, and both
+  // must see the same coefficients (see the context's staging)
+  mh.eval_table(theta, fp64, out.data(), false);
   std::memcpy(out.data() + toff, theta, (size_t)mh.P * 8);
 }
 
