@@ -272,7 +272,8 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
   for (int r = 0; r < 2 * R1; ++r) tgc[r] = thm[r] = thg[r] = Real(0);
 
   int cj12 = -1, cj13 = -1;
-  Real p12[8], p13[8], e12[4], e13[4];  // e: residues of P_0, P_1 (FP32 tables)
+  // e: residues of P_1 (elements 2, 3) of the two intervals, e0: the sum of their P_0 residues
+  Real p12[8], p13[8], e12[4], e13[4], e0r = Real(0), e0i = Real(0);
 #pragma unroll
   for (int m = 0; m < 8; ++m) p12[m] = p13[m] = Real(0);
 #pragma unroll
@@ -308,18 +309,22 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
     Real ai = p12[1] + x12 * (p12[3] + x12 * (p12[5] + x12 * p12[7]));
     ar += p13[0] + x13 * (p13[2] + x13 * (p13[4] + x13 * p13[6]));
     ai += p13[1] + x13 * (p13[3] + x13 * (p13[5] + x13 * p13[7]));
-    if constexpr (kLo) {
-      ar += (e12[0] + x12 * e12[2]) + (e13[0] + x13 * e13[2]);
-      ai += (e12[1] + x12 * e12[3]) + (e13[1] + x13 * e13[3]);
-    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       ar += cre[r] * rr[r] - cim[r] * ri[r];
       ai += cre[r] * ri[r] + cim[r] * rr[r];
-      if constexpr (kLo) {
-        ar += cre_lo[r] * rr[r] - cim_lo[r] * ri[r];
-        ai += cre_lo[r] * ri[r] + cim_lo[r] * rr[r];
+    }
+    if constexpr (kLo) {
+      // the residue terms, all small, summed among themselves and then added once
+      Real dr = e0r + x12 * e12[2] + x13 * e13[2];
+      Real di = e0i + x12 * e12[3] + x13 * e13[3];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        dr += cre_lo[r] * rr[r] - cim_lo[r] * ri[r];
+        di += cre_lo[r] * ri[r] + cim_lo[r] * rr[r];
       }
+      ar += dr;
+      ai += di;
     }
     const Real a2 = ar * ar + ai * ai;
     Real gr, gi;
@@ -381,10 +386,12 @@ __device__ __forceinline__ void run_segment(const Segment& sg, const Kin<Real>& 
       }
       if constexpr (kLo) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 2; m < 4; ++m) {
           e12[m] = O::uniform(lo[4 * cj12 + m]);
           e13[m] = O::uniform(lo[4 * cj13 + m]);
         }
+        e0r = O::uniform(lo[4 * cj12] + lo[4 * cj13]);
+        e0i = O::uniform(lo[4 * cj12 + 1] + lo[4 * cj13 + 1]);
       }
     }
   };
