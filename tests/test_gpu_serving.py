@@ -139,18 +139,19 @@ def test_invalid_submissions_are_rejected(norm, jobs):
         assert ok["status"] == 0
 
 
-def test_cancellation_at_any_point_and_teardown_with_work_in_flight(norm, jobs):
-    """Many jobs, cancelled at staggered times (queued, loading, between steps or inside one), then
-    the server closed while the rest are still running: every wait returns, the cancelled ones as
-    E_CANCELLED, the others converged or cancelled by the teardown, and an untouched job's result is
-    the one it gets alone."""
+@pytest.mark.parametrize("copy", [True, False], ids=["copied", "lent"])
+def test_cancellation_at_any_point_and_teardown_with_work_in_flight(norm, jobs, copy):
+    """Many jobs, cancelled at staggered times (queued, waiting for a loader stream, loading, between
+    steps or inside one), then the server closed while the rest are still running: every wait
+    returns, the cancelled ones as E_CANCELLED, the others converged or cancelled by the teardown,
+    and an untouched job's result is the one it gets alone; with the events copied or lent."""
     import time
     with _server(norm, "mixed") as ref_srv:
         ref = ref_srv.wait(_submit(ref_srv, jobs["D"]))
     srv = _server(norm, "mixed")
     keys = ["A", "B", "C"] * 8
-    ids = [_submit(srv, jobs[k]) for k in keys]
-    keep = _submit(srv, jobs["D"])
+    ids = [_submit(srv, jobs[k], copy=copy) for k in keys]
+    keep = _submit(srv, jobs["D"], copy=copy)
     for k, j in enumerate(ids[::2]):
         time.sleep(0.002 * (k % 4))
         srv.cancel(j)
@@ -160,5 +161,5 @@ def test_cancellation_at_any_point_and_teardown_with_work_in_flight(norm, jobs):
     for j in ids[::2]:
         assert srv.wait(j)["status"] in (-7, 0, -6)  # a job may finish before its cancel lands
     for k in ("A", "B"):
-        _submit(srv, jobs[k])
+        _submit(srv, jobs[k], copy=copy)
     srv.close()  # jobs still queued or running are cancelled; nothing hangs or faults
