@@ -117,6 +117,10 @@ int ModelHost::init(const mipwa_model* m, std::string& err) {
     th_d[i] = den;
     th_c[i] = c / den;
   }
+  inv_h.resize(N - 1);
+  for (int j = 0; j < N - 1; ++j) inv_h[j] = 1.0 / h[j];
+  inv_d.assign(th_d.size(), 0.0);
+  for (int i = 0; i < n; ++i) inv_d[i] = 1.0 / th_d[i];
   fill_kin(kin64, M, m1, m2, m3, rD);
   fill_kin(kin32, M, m1, m2, m3, rD);
   return MIPWA_OK;
@@ -126,14 +130,14 @@ void ModelHost::second_derivs(const double* zr, const double* zi, double* Mr, do
   const int n = N - 2;
   Mr[0] = Mi[0] = Mr[N - 1] = Mi[N - 1] = 0.0;
   if (n <= 0) return;
-  std::vector<double> yr(n), yi(n);
+  double yr[kMaxKnots], yi[kMaxKnots];
   for (int i = 0; i < n; ++i) {
     const int k = i + 1;
-    const double rr = 6.0 * ((zr[k + 1] - zr[k]) / h[k] - (zr[k] - zr[k - 1]) / h[k - 1]);
-    const double ri = 6.0 * ((zi[k + 1] - zi[k]) / h[k] - (zi[k] - zi[k - 1]) / h[k - 1]);
+    const double rr = 6.0 * ((zr[k + 1] - zr[k]) * inv_h[k] - (zr[k] - zr[k - 1]) * inv_h[k - 1]);
+    const double ri = 6.0 * ((zi[k + 1] - zi[k]) * inv_h[k] - (zi[k] - zi[k - 1]) * inv_h[k - 1]);
     const double a = h[k - 1];
-    yr[i] = (rr - (i > 0 ? a * yr[i - 1] : 0.0)) / th_d[i];
-    yi[i] = (ri - (i > 0 ? a * yi[i - 1] : 0.0)) / th_d[i];
+    yr[i] = (rr - (i > 0 ? a * yr[i - 1] : 0.0)) * inv_d[i];
+    yi[i] = (ri - (i > 0 ? a * yi[i - 1] : 0.0)) * inv_d[i];
   }
   for (int i = n - 1; i >= 0; --i) {
     if (i < n - 1) {
@@ -146,13 +150,15 @@ void ModelHost::second_derivs(const double* zr, const double* zi, double* Mr, do
 }
 
 void ModelHost::poly_table(const double* theta, double* out) const {
-  std::vector<double> zr(N), zi(N), Mr(N), Mi(N);
+  double zr[kMaxKnots], zi[kMaxKnots], Mr[kMaxKnots], Mi[kMaxKnots];
   for (int k = 0; k < N; ++k) {
     const double a = theta[2 * k], ph = theta[2 * k + 1];
-    zr[k] = a * std::cos(ph);
-    zi[k] = a * std::sin(ph);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    zr[k] = a * cs;
+    zi[k] = a * sn;
   }
-  second_derivs(zr.data(), zi.data(), Mr.data(), Mi.data());
+  second_derivs(zr, zi, Mr, Mi);
   // S on interval j with t = (s - s_j)/h_j:  S = P0 + P1 t + P2 t^2 + P3 t^3 with
   //   P0 = z_j, P1 = z_{j+1} - z_j - (h^2/6)(2 M_j + M_{j+1}), P2 = (h^2/2) M_j, P3 = (h^2/6)(M_{j+1} - M_j).
   for (int j = 0; j < N - 1; ++j) {
@@ -186,7 +192,8 @@ void ModelHost::res_table(const double* theta, double* out) const {
     const double dK1 = barrier_poly_d(L, zq) * rho2 * dq2_dm;
     const double dK2 = barrier_poly_d(L, zp) * rD2 * dp2_dm;
     const double kappa = std::sqrt(K1 * K2);
-    const double qpow = std::pow(std::sqrt(q2), 2 * L + 1);
+    double qpow = std::sqrt(q2);  // q^(2L+1)
+    for (int l = 0; l < L; ++l) qpow *= q2;
     const double delta = G * s * K1 / qpow;
     const double dln_delta = 2.0 / m + dK1 / K1 - 0.5 * (2 * L + 1) * dq2_dm / q2;
     double* o = out + kResWords * r;
@@ -205,16 +212,18 @@ void ModelHost::res_table(const double* theta, double* out) const {
 
 void ModelHost::eval_table(const double* theta, bool fp64, void* out, bool residues) const {
   const int nint = N - 1, tw = table_words(nint, R);
-  std::vector<double> tab(tw);
-  poly_table(theta, tab.data());
+  double tab[table_words(kMaxKnots - 1, kMaxRes)];
+  poly_table(theta, tab);
   for (int r = 0; r < R; ++r) {
     const double cm = theta[2 * N + 2 * r], ca = theta[2 * N + 2 * r + 1];
-    tab[8 * nint + 2 * r] = cm * std::cos(ca);
-    tab[8 * nint + 2 * r + 1] = cm * std::sin(ca);
+    double sn, cs;
+    sincos(ca, &sn, &cs);
+    tab[8 * nint + 2 * r] = cm * cs;
+    tab[8 * nint + 2 * r + 1] = cm * sn;
   }
-  res_table(theta, tab.data() + 8 * nint + 2 * R);
+  res_table(theta, tab + 8 * nint + 2 * R);
   if (fp64) {
-    std::memcpy(out, tab.data(), (size_t)tw * sizeof(double));
+    std::memcpy(out, tab, (size_t)tw * sizeof(double));
     return;
   }
   float* f = static_cast<float*>(out);

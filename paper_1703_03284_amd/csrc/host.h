@@ -119,6 +119,7 @@ struct ModelHost {
   int N = 0, R = 0, P = 0;
   std::vector<double> th_c;      // Thomas factors (interior unknowns)
   std::vector<double> th_d;
+  std::vector<double> inv_h, inv_d;  // 1/h and 1/th_d: the per-evaluation staging multiplies
   Kin<double> kin64{};
   Kin<float> kin32{};
 
