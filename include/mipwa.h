@@ -263,8 +263,9 @@ int mipwa_set_launch(mipwa_ctx* ctx, int blocks, int waves_per_block);
 /* ---- toy-fit serving with continuous batching -------------------------------------------------
  * A server fits many independent toy samples (Sec. 4: fits of toy samples generated from the
  * Dalitz-plot PDF) against one shared normalisation sample.  Jobs wait until their device footprint
- * fits the HBM budget, then load (cell sort and resonance cache on their own stream) and run the BFGS
- * fit of mipwa_fit in a worker thread.  Every evaluation a job needs is batched with the pending
+ * fits the HBM budget, then load (cell sort and resonance cache, a few loads at a time, first come
+ * first served) and run the BFGS fit of mipwa_fit in a worker thread; a job's result is available
+ * before its device memory has gone back to the server's pool.  Every evaluation a job needs is batched with the pending
  * evaluations of other active jobs into a single launch of the streaming kernel.  Up to two steps are
  * in flight: while one runs, the next is formed from the jobs outside it and queued behind it, so the
  * jobs' host work overlaps the device's (a step formed with none in flight takes at most half of the

@@ -2,12 +2,13 @@
 //
 // Each submitted job is a maximum-likelihood fit (the fit of Sec. 2 / Sec. 4 on a toy sample) of its
 // own events against a normalisation sample shared by the server.  Jobs wait in a queue until their
-// device footprint fits the HBM budget; an admitted job loads its events (cell sort, resonance cache)
-// and forms, at its own (fixed) masses and widths, the per-cell moments of the shared normalisation
-// points, on its own stream and thread, then runs the BFGS fit in that thread.  The normalisation
-// points are cell-sorted once per knot grid and shared; with the shapes fixed, each evaluation takes
-// the normalisation integral as a quadratic form over the job's moments instead of a sweep over the
-// points.  Every evaluation a job asks for is posted to the scheduler, which gathers the pending
+// device footprint fits the HBM budget; an admitted job's thread loads its events (cell sort,
+// resonance cache) on one of a few loader streams, taken first come first served, then runs the BFGS
+// fit.  The normalisation points are cell-sorted once per knot grid and shared, and so are their
+// per-cell moments at each set of resonance shapes (formed by the first job that needs them); with the
+// shapes fixed, each evaluation takes the normalisation integral as a quadratic form over those
+// moments instead of a sweep over the points.  Device memory comes from a pool owned by the server and
+// goes back to it in stream order, without waiting for the device.  Every evaluation a job asks for is posted to the scheduler, which gathers the pending
 // evaluations of active jobs into one launch of the streaming kernel (one data segment and one cell
 // segment per job).  Up to two such steps are in flight on the server's stream, so that one group of
 // jobs computes its next points while the other's step runs.  A job's block count depends only on
