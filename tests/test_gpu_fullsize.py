@@ -58,6 +58,27 @@ def test_headline_nll_full_size(headline, prec, tol):
     ctx.close()
 
 
+def test_headline_two_part_sweep_is_bitwise_in_either_order(headline):
+    """At 10M + 10M points the sweep reads 520 MB, between one and three times the Infinity Cache, so
+    each wave sweeps its tiles in two parts and consecutive evaluations take the parts in opposite
+    orders: every other evaluation must give bitwise the same -2 ln L and gradient.  The same sample
+    with the quadratic form reads 240 MB, which fits the cache, and is swept in one part."""
+    from paper_1703_03284_amd import MIXED, NORM_QFORM, context_for
+    wl, table, ev, nm, th, v_o, g_o = headline
+    d = wl.decay
+    for qform in (False, True):
+        ctx = context_for(d, wl.knots(), wl.resonances, MIXED)
+        if qform:
+            ctx.set_norm_mode(NORM_QFORM)
+        ctx.set_eff_table(table, d.smin, d.smax)
+        ctx.load_events(*ev)
+        ctx.load_norm(*nm)
+        runs = [ctx.eval(th) for _ in range(3)]
+        for v, g in runs[1:]:
+            assert v == runs[0][0] and np.array_equal(g, runs[0][1])
+        ctx.close()
+
+
 def test_headline_mixed_gradient_vs_fp64_full_size(headline):
     from paper_1703_03284_amd import context_for
     wl, table, ev, nm, th, _, _ = headline
