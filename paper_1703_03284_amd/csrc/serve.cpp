@@ -7,13 +7,13 @@
 // fit.  The normalisation points are cell-sorted once per knot grid and shared, and so are their
 // per-cell moments at each set of resonance shapes (formed by the first job that needs them); with the
 // shapes fixed, each evaluation takes the normalisation integral as a quadratic form over those
-// moments instead of a sweep over the points.  Device memory comes from a pool owned by the server and
-// goes back to it in stream order, without waiting for the device.  Every evaluation a job asks for is posted to the scheduler, which gathers the pending
-// evaluations of active jobs into one launch of the streaming kernel (one data segment and one cell
-// segment per job).  Up to two such steps are in flight on the server's stream, so that one group of
-// jobs computes its next points while the other's step runs.  A job's block count depends only on
-// its own sizes and every job is swept in one part, so its reduction order, and therefore its result,
-// is bitwise the same alone or in any mix.
+// moments instead of a sweep over the points.  Device memory comes from a pool owned by the server
+// and goes back to it in stream order, without waiting for the device.  Every evaluation a job asks
+// for is posted to the scheduler, which gathers the pending evaluations of active jobs into one launch
+// of the streaming kernel (one data segment and one cell segment per job).  Up to two such steps are
+// in flight on the server's stream, so that one group of jobs computes its next points while the
+// other's step runs.  A job's block count depends only on its own sizes and every job is swept in one
+// part, so its reduction order, and therefore its result, is bitwise the same alone or in any mix.
 #include <hip/hip_runtime.h>
 #include <immintrin.h>
 
