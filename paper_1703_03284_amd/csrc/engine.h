@@ -127,14 +127,14 @@ hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* d_segs, const 
                        const ArgTable* args, int parts, int order, hipStream_t stream, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
 // Parts for a sweep that reads `bytes` per evaluation: the alternation pays where the part read last
-// is still in the 256 MB Infinity Cache of an MI355X when the next evaluation starts (measured at
-// 520 MB: 101 -> 95.5 us with two parts; four parts measured no gain), and costs the extra flushes
-// where the stream is several times the cache (measured: +2.7% at 1 GB).
-// A stream that fits the cache whole is served from it by one sweep in the same order every time
-// (quadratic-form headline, 240 MB: 53.6 -> 50.3 us with one part instead of two).
+// is still in the 256 MB Infinity Cache of an MI355X when the next evaluation starts, and costs the
+// extra flushes where the stream fits the cache (one pass in the same order each time is then served
+// from it) or is several times its size.  Measured (mixed k_eval, us, one part / two parts): 260 MB
+// 54.4 / 55.7, 312 MB 62.1 / 64.2, 416 MB 86.2 / 81.7, 520 MB 103.9 / 98.3, 624 MB 121.6 / 116.8,
+// 832 MB 157.0 / 153.9; 1 GB (FP64) +2.7 % with two; four parts measured no gain at 520 MB.
 constexpr double kInfinityCacheBytes = 256.0 * (1 << 20);
 inline int sweep_parts(double bytes) {
-  return bytes <= kInfinityCacheBytes ? 1 : bytes <= 3.0 * kInfinityCacheBytes ? 2 : 1;
+  return bytes <= 1.4 * kInfinityCacheBytes ? 1 : bytes <= 3.5 * kInfinityCacheBytes ? 2 : 1;
 }
 // group sums (one block per task (segment, group)) then one finishing block per job
 hipError_t launch_reduce(const Segment* d_segs, const Job* d_jobs, const int2* d_tasks, int n_tasks, int n_jobs,
