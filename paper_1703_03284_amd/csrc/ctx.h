@@ -45,6 +45,7 @@ struct mipwa_ctx {
   double* h_out_dev = nullptr;   // device view of h_out
   mipwa::Segment h_segs[2];
   mipwa::Job h_jobs[2];          // host copies: the finish takes the job descriptor by value
+  mipwa::GroupPlan h_plan{};     // the group sums' layout, passed by value as well
   int blocks_cfg = 512, waves_cfg = 0, waves_eff = 4;
   int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0, n_tasks = 0;
   bool launch_dirty = true;

@@ -136,10 +136,20 @@ constexpr double kInfinityCacheBytes = 256.0 * (1 << 20);
 inline int sweep_parts(double bytes) {
   return bytes <= 1.4 * kInfinityCacheBytes ? 1 : bytes <= 3.5 * kInfinityCacheBytes ? 2 : 1;
 }
-// group sums (one block per task (segment, group)) then one finishing block per job
+// The group sums of a single job's two segments, passed by value (no task, segment or job descriptor
+// to load first): block b < G_d sums data group b, block G_d + g normalisation group g.
+struct GroupPlan {
+  const double* records[2];  // the segments' block records (device)
+  double* grec;              // (G_d + G_n) x rs group records (device)
+  int n_blocks[2];
+  int G_d, G_n, rs, pad;
+};
+// group sums (one block per task (segment, group), or per group of `plan` when given: then d_tasks
+// and n_tasks are unused and n_jobs is 1) then one finishing block per job
 hipError_t launch_reduce(const Segment* d_segs, const Job* d_jobs, const int2* d_tasks, int n_tasks, int n_jobs,
                          const ArgTable* args, hipStream_t stream, unsigned long long seq = 0,
-                         double* out_override = nullptr, const Job* single = nullptr);
+                         double* out_override = nullptr, const Job* single = nullptr,
+                         const GroupPlan* plan = nullptr);
 // Copy `bytes` (a multiple of 16, both addresses 16-byte aligned) from mapped host memory to device
 // memory with a kernel on `stream`.  Per-evaluation tables go up this way, ordered with the kernels
 // that read them like any other kernel on the stream.

@@ -993,20 +993,33 @@ __global__ __launch_bounds__(512) void k_eval(const Segment* __restrict__ segs, 
 }
 
 // ---------------------------------------------------------------------------------------------
-// K3: group sums.  Task t = (segment, group): the records of blocks [32 g, 32 g + 32) of the segment,
-// summed in block order into the job's group record.  No cross-block communication inside a kernel:
-// the kernel boundary after the streaming kernel makes its records visible.
+// K3: group sums.  Group g of a segment: the records of its blocks [32 g, 32 g + 32), summed in block
+// order into the job's group record.  No cross-block communication inside a kernel: the kernel
+// boundary after the streaming kernel makes its records visible.  One block per task (segment, group)
+// of `tasks`, or, with tasks == nullptr, per group of the single job described by `plan`.
 
 __global__ __launch_bounds__(512) void k_group_sum(const Segment* __restrict__ segs, const Job* __restrict__ jobs,
-                                                   const int2* __restrict__ tasks) {
-  const int2 tk = tasks[blockIdx.x];
-  const Segment& sg = segs[tk.x];
-  const Job& jb = jobs[sg.job];
-  const int g = tk.y;
-  const int rs = sg.rs;
-  const int gsz = min(kGroup, sg.n_blocks - g * kGroup);
-  const double* rb = sg.records + (long long)g * kGroup * rs;
-  double* go = jb.grec + (long long)(sg.g0 + g) * rs;
+                                                   const int2* __restrict__ tasks, GroupPlan plan) {
+  const double* rb;
+  double* go;
+  int rs, gsz;
+  if (tasks) {
+    const int2 tk = tasks[blockIdx.x];
+    const Segment& sg = segs[tk.x];
+    const Job& jb = jobs[sg.job];
+    const int g = tk.y;
+    rs = sg.rs;
+    gsz = min(kGroup, sg.n_blocks - g * kGroup);
+    rb = sg.records + (long long)g * kGroup * rs;
+    go = jb.grec + (long long)(sg.g0 + g) * rs;
+  } else {
+    const int k = (int)blockIdx.x < plan.G_d ? 0 : 1;
+    const int g = k ? (int)blockIdx.x - plan.G_d : (int)blockIdx.x;
+    rs = plan.rs;
+    gsz = min(kGroup, plan.n_blocks[k] - g * kGroup);
+    rb = plan.records[k] + (long long)g * kGroup * rs;
+    go = plan.grec + (long long)(k ? plan.G_d + g : g) * rs;
+  }
   for (int f = threadIdx.x; f < rs; f += blockDim.x) {
     // every load reads a valid record (the index is clamped into the group) and is issued without a
     // branch; records past the group's end are then dropped from the sum
@@ -1419,10 +1432,15 @@ hipError_t launch_eval(bool fp64, int R, bool otf, const Segment* segs, const in
 
 hipError_t launch_reduce(const Segment* segs, const Job* jobs, const int2* tasks, int n_tasks, int n_jobs,
                          const ArgTable* targ, hipStream_t st,
-                         unsigned long long seq, double* out_override, const Job* single) {
+                         unsigned long long seq, double* out_override, const Job* single, const GroupPlan* plan) {
   (void)hipGetLastError();
   static const ArgTable empty{};
-  k_group_sum<<<n_tasks, 512, 0, st>>>(segs, jobs, tasks);
+  if (plan) {
+    if (n_jobs != 1 || plan->G_d < 1 || plan->G_n < 1) return hipErrorInvalidValue;
+    k_group_sum<<<plan->G_d + plan->G_n, 512, 0, st>>>(segs, jobs, nullptr, *plan);
+  } else {
+    k_group_sum<<<n_tasks, 512, 0, st>>>(segs, jobs, tasks, GroupPlan{});
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   static const Job none{};

@@ -179,6 +179,15 @@ int mipwa_ctx::rebuild_launch() {
   HIPCHK(hipMemcpy(d_job.p, jb, sizeof(jb), hipMemcpyHostToDevice), "job upload");
   h_jobs[0] = jb[0];
   h_jobs[1] = jb[1];
+  h_plan = GroupPlan{};
+  for (int k = 0; k < 2; ++k) {
+    h_plan.records[k] = sg[k].records;
+    h_plan.n_blocks[k] = sg[k].n_blocks;
+  }
+  h_plan.grec = d_grec.as<double>();
+  h_plan.G_d = L.G_d;
+  h_plan.G_n = L.G_n;
+  h_plan.rs = L.rs;
   launch_dirty = false;
   return MIPWA_OK;
 }
@@ -258,7 +267,7 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigne
                      kind == 1 ? ev_t[cs][2] : nullptr),
          "likelihood kernel");
   HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), d_tasks.as<int2>(), n_tasks, 1,
-                       use_arg ? &h_args : nullptr, st, s, out, &h_jobs[to_host ? 0 : 1]),
+                       use_arg ? &h_args : nullptr, st, s, out, &h_jobs[to_host ? 0 : 1], &h_plan),
          "reduction kernels");
   HIPCHK(hipEventRecord(ev_done, st), "event");
   last_st = st;
