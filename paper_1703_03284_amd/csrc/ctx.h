@@ -40,14 +40,14 @@ struct mipwa_ctx {
   int arg_theta_off = 0;
   mipwa::ArgTable h_args{};
 
-  mipwa::DevBuf d_segs, d_block_seg, d_records, d_grec, d_tasks, d_out, d_job, d_res64;
+  mipwa::DevBuf d_segs, d_block_seg, d_records, d_grec, d_out, d_job, d_res64;
   mipwa::HostBuf h_out;          // mapped, coherent: the finish writes the results here
   double* h_out_dev = nullptr;   // device view of h_out
   mipwa::Segment h_segs[2];
   mipwa::Job h_jobs[2];          // host copies: the finish takes the job descriptor by value
   mipwa::GroupPlan h_plan{};     // the group sums' layout, passed by value as well
   int blocks_cfg = 512, waves_cfg = 0, waves_eff = 4;
-  int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0, n_tasks = 0;
+  int n_blocks = 0, nb_d = 0, nb_n = 0, rs = 0;
   bool launch_dirty = true;
 
   // Timing events: two sets [before the first launch, sweep start, sweep end, after the finish] used

@@ -144,12 +144,6 @@ int mipwa_ctx::rebuild_launch() {
   const bool qf = use_qform();
   HIPCHK(d_records.alloc((size_t)L.B * L.rs * sizeof(double)), "records allocation");
   HIPCHK(d_grec.alloc((size_t)(L.G_d + L.G_n) * L.rs * sizeof(double)), "group records allocation");
-  std::vector<int2> tasks;
-  for (int g = 0; g < L.G_d; ++g) tasks.push_back(int2{0, g});
-  for (int g = 0; g < L.G_n; ++g) tasks.push_back(int2{1, g});
-  n_tasks = (int)tasks.size();
-  HIPCHK(d_tasks.alloc(tasks.size() * sizeof(int2)), "task allocation");
-  HIPCHK(hipMemcpy(d_tasks.p, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice), "task upload");
   std::vector<int2> bs(L.B);
   for (int b = 0; b < L.B; ++b) bs[b] = b < L.nb_d ? int2{0, b} : int2{1, b - L.nb_d};
   HIPCHK(d_block_seg.alloc(L.B * sizeof(int2)), "block map allocation");
@@ -266,7 +260,8 @@ int mipwa_ctx::enqueue_kernels(hipStream_t st, bool to_host, bool timed, unsigne
                      use_arg ? &h_args : nullptr, sweep_parts_eff, sweep_order, st, kind == 1 ? ev_t[cs][1] : nullptr,
                      kind == 1 ? ev_t[cs][2] : nullptr),
          "likelihood kernel");
-  HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), d_tasks.as<int2>(), n_tasks, 1,
+  // the group sums take their layout from h_plan: no task list
+  HIPCHK(launch_reduce(d_segs.as<Segment>(), d_job.as<Job>() + (to_host ? 0 : 1), nullptr, 0, 1,
                        use_arg ? &h_args : nullptr, st, s, out, &h_jobs[to_host ? 0 : 1], &h_plan),
          "reduction kernels");
   HIPCHK(hipEventRecord(ev_done, st), "event");
