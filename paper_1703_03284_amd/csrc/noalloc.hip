@@ -55,15 +55,13 @@ struct SetupArgs {
   Segment seg[2];
   Job job;
   double res64[kResWords * kMaxRes];
-  int nb_d, B, G_d, T, n_res64, pad;
+  int nb_d, B, n_res64, pad;
 };
 
 __global__ __launch_bounds__(256) void k_noalloc_setup(SetupArgs a, Segment* __restrict__ seg, Job* __restrict__ job,
-                                                       double* __restrict__ res64, int2* __restrict__ block_map,
-                                                       int2* __restrict__ tasks) {
+                                                       double* __restrict__ res64, int2* __restrict__ block_map) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < a.B) block_map[i] = i < a.nb_d ? int2{0, i} : int2{1, i - a.nb_d};
-  if (i < a.T) tasks[i] = i < a.G_d ? int2{0, i} : int2{1, i - a.G_d};
   if (i < a.n_res64) res64[i] = a.res64[i];
   if (i == 0) {
     seg[0] = a.seg[0];
@@ -94,7 +92,7 @@ extern "C" int mipwa_eval_noalloc(mipwa_ctx* ctx, void* stream, double* d_out) {
   NACHK(scratch_base(ctx->device, &base), "scratch address");
   const mipwa_ctx::LaunchPlan L = ctx->plan_launch();
   const int T = L.G_d + L.G_n;
-  // scratch layout: segments | job | resonance constants | block map | tasks | records | group records
+  // scratch layout: segments | job | resonance constants | block map | records | group records
   size_t off = 0;
   const size_t o_seg = off;
   off += up(2 * sizeof(Segment));
@@ -104,8 +102,6 @@ extern "C" int mipwa_eval_noalloc(mipwa_ctx* ctx, void* stream, double* d_out) {
   off += up(sizeof(double) * kResWords * kMaxRes);
   const size_t o_bmap = off;
   off += up(sizeof(int2) * L.B);
-  const size_t o_tasks = off;
-  off += up(sizeof(int2) * T);
   const size_t o_rec = off;
   off += up(sizeof(double) * (size_t)L.B * L.rs);
   const size_t o_grec = off;
@@ -119,7 +115,6 @@ extern "C" int mipwa_eval_noalloc(mipwa_ctx* ctx, void* stream, double* d_out) {
   Job* d_job = reinterpret_cast<Job*>(base + o_job);
   double* d_res = reinterpret_cast<double*>(base + o_res);
   int2* d_bmap = reinterpret_cast<int2*>(base + o_bmap);
-  int2* d_tasks = reinterpret_cast<int2*>(base + o_tasks);
   double* d_rec = reinterpret_cast<double*>(base + o_rec);
   double* d_grec = reinterpret_cast<double*>(base + o_grec);
 
@@ -136,16 +131,14 @@ extern "C" int mipwa_eval_noalloc(mipwa_ctx* ctx, void* stream, double* d_out) {
   a.job.seq_out = nullptr;
   a.nb_d = L.nb_d;
   a.B = L.B;
-  a.G_d = L.G_d;
-  a.T = T;
   const bool rebuild = !ctx->otf && ctx->shapes_changed();
   if (rebuild) {
     ctx->mh.res_table(ctx->theta.data(), a.res64);
     a.n_res64 = kResWords * ctx->mh.R;
   }
-  const int n_setup = std::max(std::max(L.B, T), std::max(a.n_res64, 1));
+  const int n_setup = std::max(L.B, std::max(a.n_res64, 1));
   (void)hipGetLastError();
-  k_noalloc_setup<<<(n_setup + 255) / 256, 256, 0, st>>>(a, d_seg, d_job, d_res, d_bmap, d_tasks);
+  k_noalloc_setup<<<(n_setup + 255) / 256, 256, 0, st>>>(a, d_seg, d_job, d_res, d_bmap);
   NACHK(hipGetLastError(), "descriptor kernel");
   if (rebuild) {
     // the resonance amplitudes of both point sets at the new masses and widths; the context's own
@@ -165,7 +158,17 @@ extern "C" int mipwa_eval_noalloc(mipwa_ctx* ctx, void* stream, double* d_out) {
                     ctx->fp64 ? (const void*)&ctx->mh.kin64 : (const void*)&ctx->mh.kin32, args, L.parts, ctx->sweep_order,
                     st),
         "likelihood kernel");
-  NACHK(launch_reduce(d_seg, d_job, d_tasks, T, 1, args, st, 0, d_out, &a.job), "reduction kernels");
+  // the group sums take the layout by value: no task list in the scratch
+  GroupPlan plan{};
+  for (int k = 0; k < 2; ++k) {
+    plan.records[k] = a.seg[k].records;
+    plan.n_blocks[k] = a.seg[k].n_blocks;
+  }
+  plan.grec = d_grec;
+  plan.G_d = L.G_d;
+  plan.G_n = L.G_n;
+  plan.rs = L.rs;
+  NACHK(launch_reduce(d_seg, d_job, nullptr, 0, 1, args, st, 0, d_out, &a.job, &plan), "reduction kernels");
   NACHK(hipEventRecord(ctx->ev_done, st), "event");
   ctx->last_st = st;
   ctx->sweep_order ^= 1;
