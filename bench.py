@@ -269,10 +269,10 @@ def small_fit_vs_oracle():
 
 def serving(n_jobs, precision, rate_factor=0.8, log_every=32, borrow=True):
     """Toy-fit serving: n_jobs fits (event counts log-uniform in [1e4, 5e6], knots in {20,30,40,50},
-    rho(770)+f2(1270), shapes fixed) against one shared 2M-point normalisation sample.  Run 1 submits
-    every job at t=0 (capacity); run 2 submits them at Poisson arrival times with rate
-    rate_factor x capacity and reports fits/s and p50/p99 time-to-fit.  borrow: the jobs' event arrays
-    are lent to the server (read when each job loads) instead of copied at submission."""
+    rho(770)+f2(1270), shapes held at their table values) against one shared 2M-point normalisation
+    sample.  Run 1 submits every job at t=0 (capacity); run 2 submits them at Poisson arrival times
+    with rate rate_factor x capacity and reports fits/s and p50/p99 time-to-fit.  borrow: the jobs'
+    event arrays are lent to the server (read when each job loads) instead of copied at submission."""
     import synth
     from paper_1703_03284_amd import FP64, Server, context_for
     wl = synth.C1
@@ -288,7 +288,7 @@ def serving(n_jobs, precision, rate_factor=0.8, log_every=32, borrow=True):
             gens[N] = context_for(d, synth.uniform_knots(d, N), wl.resonances, FP64)
         truth = synth.truth_theta(N, wl.resonances, seed)
         s12, s13, _ = gens[N].toy(truth, n, seed, n_probe=200_000)
-        payload.append((synth.uniform_knots(d, N), s12, s13, synth.perturb_theta(truth, N, wl.n_res, seed + 7)))
+        payload.append((synth.uniform_knots(d, N), s12, s13, synth.fit_start(truth, N, wl.n_res, seed + 7)))
     for g in gens.values():
         g.close()
     n_events = sum(len(p[1]) for p in payload)

@@ -251,6 +251,16 @@ def perturb_theta(theta: np.ndarray, n_knots: int, n_res: int, seed: int) -> np.
     return th
 
 
+def fit_start(theta: np.ndarray, n_knots: int, n_res: int, seed: int, float_shapes: bool = False) -> np.ndarray:
+    """Seeded start of a toy fit: perturb_theta for the floated parameters, while the held ones (the
+    reference coefficient; the masses and widths unless floated) keep the values the toy was generated
+    with, as a fit holds them at the model's known values."""
+    th = perturb_theta(theta, n_knots, n_res, seed)
+    held = fixed_mask(n_knots, n_res, float_shapes).astype(bool)
+    th[held] = np.asarray(theta, dtype=np.float64)[held]
+    return th
+
+
 def fixed_mask(n_knots: int, n_res: int, float_shapes: bool = False) -> np.ndarray:
     """1 = held fixed.  The first resonance coefficient is the reference (global phase and scale);
     masses and widths are fixed unless float_shapes."""
