@@ -23,7 +23,7 @@ constexpr int kMaxRes = 4;
 constexpr int kSwavePolar = 0, kSwaveCartesian = 1, kSwaveIsobar = 2;
 constexpr int kMaxKnots = 128;
 // Doubles of the per-model constants: Thomas factors and interval widths.
-__host__ __device__ inline int consts_words(int N) { return 3 * N - 5; }
+__host__ __device__ constexpr int consts_words(int N) { return 3 * N - 5; }
 // Words per resonance in the evaluation table:
 // m^2, kappa, delta, rho^2, L, m, dln(kappa)/dm, d(delta)/dm, d(delta)/dGamma, unused.
 constexpr int kResWords = 10;
@@ -86,7 +86,7 @@ struct Job {
   int swave;             // parameter form of the S-wave (kSwave*): the layout of the gradient written
 };
 
-__host__ __device__ inline int n_groups(int n_blocks) { return (n_blocks + kGroup - 1) / kGroup; }
+__host__ __device__ constexpr int n_groups(int n_blocks) { return (n_blocks + kGroup - 1) / kGroup; }
 
 // Small per-evaluation tables travel in the launch's kernel arguments: [table in working precision |
 // theta (FP64) at theta_off bytes].  A segment with table == nullptr and a job with tab64 == nullptr
@@ -98,15 +98,15 @@ struct ArgTable {
 
 // Record layout (doubles): [8 * nint spline-polynomial partials (interval j, power m, re/im)]
 // [sum] [2R: sum g conj(R_r)] [OTF: 2R sum g conj(dR_r/dm), 2R sum g conj(dR_r/dGamma)].
-__host__ __device__ inline int record_size(int nint, int R, bool otf) { return 8 * nint + 1 + 2 * R + (otf ? 4 * R : 0); }
-__host__ __device__ inline int table_words(int nint, int R) { return 8 * nint + 2 * R + kResWords * R; }
+__host__ __device__ constexpr int record_size(int nint, int R, bool otf) { return 8 * nint + 1 + 2 * R + (otf ? 4 * R : 0); }
+__host__ __device__ constexpr int table_words(int nint, int R) { return 8 * nint + 2 * R + kResWords * R; }
 // An FP32 table is followed by the rounding residues of the coefficients that set the amplitude's size,
 // [P_0 re, P_0 im, P_1 re, P_1 im of each interval | c_r re, im]: a coefficient is its FP32 word plus
 // its residue, which carries the FP64 value to about 2^-48 (a rounding of the coefficients alone would
 // act like a shift of theta by one FP32 ulp, coherent over every point).
-__host__ __device__ inline int table_lo_words(int nint, int R) { return 4 * nint + 2 * R; }
+__host__ __device__ constexpr int table_lo_words(int nint, int R) { return 4 * nint + 2 * R; }
 // words of the table in the working precision
-__host__ __device__ inline int table_real_words(int nint, int R, bool fp64) {
+__host__ __device__ constexpr int table_real_words(int nint, int R, bool fp64) {
   return table_words(nint, R) + (fp64 ? 0 : table_lo_words(nint, R));
 }
 
