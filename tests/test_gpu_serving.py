@@ -82,6 +82,28 @@ def test_result_alone_equals_result_in_the_mix(norm, jobs, precision):
     assert st["n_done"] == 4 and st["mean_batch"] > 1.0
 
 
+def test_jobs_with_the_same_shapes_share_moments_without_changing_results(norm, jobs):
+    # held shapes at their table values: two jobs with the same knots use one set of normalisation
+    # moments, formed by whichever loads first; a third job with the same knots but shapes of its own
+    # gets its own.  The first job's fit is bitwise the one it gets alone.
+    wl = synth.C1
+    held = {}
+    for k in ("A", "C"):
+        kn, truth, _, s12, s13 = jobs[k]
+        held[k] = (kn, truth, synth.fit_start(truth, len(kn), wl.n_res, 100 + ord(k)), s12, s13)
+    with _server(norm) as s1:
+        alone = s1.wait(_submit(s1, held["A"]))
+    with _server(norm) as s2:
+        ids = [_submit(s2, held["C"]), _submit(s2, jobs["C"]), _submit(s2, held["A"])]
+        res = [s2.wait(i) for i in ids]
+    assert alone["status"] == 0 and all(r["status"] == 0 for r in res)
+    assert np.array_equal(alone["theta"], res[2]["theta"])
+    assert alone["nll"] == res[2]["nll"] and alone["n_eval"] == res[2]["n_eval"]
+    # the held parameters stay where the start put them (the reference phase up to the fold's rounding)
+    fx = synth.fixed_mask(len(held["A"][0]), wl.n_res).astype(bool)
+    assert np.allclose(res[2]["theta"][fx], held["A"][1][fx], rtol=0, atol=1e-12)
+
+
 def test_serving_fit_agrees_with_single_context_fit(norm, jobs):
     from paper_1703_03284_amd import FP64, context_for
     wl = synth.C1
