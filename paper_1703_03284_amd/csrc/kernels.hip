@@ -12,8 +12,9 @@
 // registers).  Point streams are SoA pairs (t12,t13), (s12,s13), w, and one complex plane per
 // resonance, read coalesced.  Each wave owns a contiguous range of tiles, keeps its adjoint partials
 // in registers while the cell does not change, and folds them into a wave-private LDS histogram of
-// spline intervals when it does.  Blocks write fixed-size FP64 records; a second kernel reduces them
-// in a fixed order (bitwise reproducible) and runs the FP64 finish.
+// spline intervals when it does.  Blocks write fixed-size FP64 records; two more kernels reduce them
+// in a fixed order (bitwise reproducible): group sums of 32 records, then one block per job that sums
+// the groups and runs the FP64 finish.
 #include <algorithm>
 #include <cstdint>
 #include <type_traits>
