@@ -198,7 +198,7 @@ struct mipwa_server {
   hipStream_t stream = nullptr;
   // Device memory of the jobs and the normalisation sets: a stream-ordered pool that keeps what is
   // freed, so that loading and retiring jobs neither waits for the device (as a plain free does,
-  // stalling every other job's loads and the steps' launches) nor returns memory to the driver.
+  // stalling every other job's loads and the steps' launches) nor hands memory back to the HIP runtime.
   // A job's memory is freed in the order of `stream`, after every step that may use it.
   hipMemPool_t pool = nullptr;
   // Loads run one per loader stream at a time, in about the order jobs are admitted: many loads at
