@@ -295,9 +295,11 @@ int mipwa_server_create(int device, int precision, size_t hbm_budget_bytes, mipw
 int mipwa_server_set_norm(mipwa_server* s, const double* s12, const double* s13, const double* w, int64_t n);
 /* Queue one fit: model, n events (host arrays, copied), start theta0 (P doubles), fixed mask (P bytes,
  * nullable: the first resonance coefficient and every mass and width fixed), options (nullable:
- * tol_edm 1e-4, max_iter 1000, no Hessian).  *job_id receives the job's id.  Errors: E_INVAL (model,
- * theta0, a floated mass or width), E_STATE (no normalisation sample), E_NOMEM (the job alone exceeds
- * the budget). */
+ * tol_edm 1e-4, max_iter 1000, no Hessian).  The masses and widths stay at theta0's values; jobs with
+ * the same knots and the same masses and widths share one set of normalisation moments (formed by the
+ * first of them to load, the same numbers whichever does).  *job_id receives the job's id.  Errors:
+ * E_INVAL (model, theta0, a floated mass or width), E_STATE (no normalisation sample), E_NOMEM (the job
+ * alone exceeds the budget). */
 int mipwa_server_submit(mipwa_server* s, const mipwa_model* model, const double* s12, const double* s13, int64_t n,
                         const double* theta0, const unsigned char* fixed, const mipwa_fit_opts* opts,
                         int64_t* job_id);
